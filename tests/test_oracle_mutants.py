@@ -1,0 +1,51 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check a pin trips.
+
+Each mutant is a one-line textual change to oracle/oracle.c, compiled into a
+temporary library; the pins of ``oracle_pins`` run against it and at least one
+must fail.  This shows the pins constrain every part of the oracle: twiddle
+signs and indices, strides of the axis passes, the brute-force sum, the
+16-bit rounding and exponent rule, and the energy gradient.
+"""
+import pytest
+
+import oracle
+import oracle_pins as P
+
+MUTANTS = {
+    "complex product sign": ("im += t[2 * q] * c[1] + t[2 * q + 1] * c[0];",
+                             "im += t[2 * q] * c[1] - t[2 * q + 1] * c[0];"),
+    "combine drops s*m": ("long e = ((long)q * kk) % n;", "long e = ((long)q * k) % n;"),
+    "y stride uses ny": ("(axis == 1 ? (long)nx : (long)nx * ny)",
+                         "(axis == 1 ? (long)ny : (long)nx * ny)"),
+    "y pencil base uses nz": ("base = z * (long)nx * ny + x;", "base = z * (long)nx * nz + x;"),
+    "naive drops a term": ("re += fr * tr - fi * ti;", "re += fr * tr;"),
+    "naive wrong index": ("wy + 2 * (((long)y * ky) % ny)", "wy + 2 * (((long)y * kx) % ny)"),
+    "root table ignores sign": ("w[2 * e + 1] = (double)sign * sin(a);",
+                                "w[2 * e + 1] = sin(a);"),
+    "gradient drops factor 2": ("p[2 * (b * vol + i)] *= 2.0 * V[i];",
+                                "p[2 * (b * vol + i)] *= V[i];"),
+    "gradient uses inverse": ("err = oracle_fft3d(nx, ny, nz, batch, -1, p, grad);",
+                              "err = oracle_fft3d(nx, ny, nz, batch, +1, p, grad);"),
+    "psi uses forward": ("int err = oracle_fft3d(nx, ny, nz, batch, +1, c, p);",
+                         "int err = oracle_fft3d(nx, ny, nz, batch, -1, c, p);"),
+    "exponent off by one": ("e = ilogb(m) - 14;", "e = ilogb(m) - 15;"),
+    "ties round up": ("return fmod(f, 2.0) == 0.0 ? f : f + 1.0;", "return f + 1.0;"),
+    "no subnormal quantum": ("if (e < emin) e = emin;", "(void)emin;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = oracle.source_text()
+    assert src.count(old) == 1, "mutation site not found: %s" % name
+    lib = oracle.build_variant(src.replace(old, new), str(tmp_path / "libmutant.so"))
+    caught = []
+    with oracle.variant(lib):
+        for pin in P.ALL_PINS:
+            try:
+                pin()
+            except Exception as e:          # noqa: BLE001 -- any failure counts
+                caught.append((pin.__name__, type(e).__name__))
+                break
+    assert caught, "no pin caught mutant %r" % name
