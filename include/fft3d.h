@@ -1,0 +1,126 @@
+/*
+ * fft3d.h -- C ABI of libfft3d.so, a complex-to-complex 3D FFT for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operation is Eq. (1) of Ramaswami, Kenter, Kuehne, Plessl, "Efficient
+ * Ab-Initio Molecular Dynamic Simulations by Offloading Fast Fourier
+ * Transformations to FPGAs" (Section II):
+ *
+ *   out[b][kz][ky][kx] = sum_{z,y,x} in[b][z][y][x]
+ *                        * exp(s * 2 pi i * (x kx / Nx + y ky / Ny + z kz / Nz))
+ *
+ * with s = -1 (FFT3D_FORWARD, Eq. (1) itself: W_N = exp(-2 pi i / N)) or
+ * s = +1 (FFT3D_INVERSE, the unnormalised inverse; the paper defines no
+ * inverse, and this library follows the convention that inverse(forward(f))
+ * = Nx Ny Nz f).  No normalisation is applied in either direction.  The
+ * transform is computed, as Section II decomposes it, as batched 1D FFTs
+ * along x, then y, then z.
+ *
+ * Data layout: C order [batch][z][y][x], x contiguous, complex values as
+ * interleaved (re, im) pairs.  FFT3D_FP32 buffers hold complex64 (8 bytes per
+ * point).  Output is in natural order, in the same layout as the input.
+ *
+ * Memory: every data pointer passed to an exec call is a DEVICE pointer
+ * (hipMalloc / torch CUDA tensor memory) on the device the plan was created
+ * on, aligned to 16 bytes.  The caller owns all buffers and the stream.  A
+ * plan owns its device-side tables (allocated at plan time, freed by
+ * fft3d_destroy); execution never allocates and never synchronises the host.
+ *
+ * Streams: `stream` is a hipStream_t (NULL selects the null stream).  Calls
+ * are enqueued asynchronously in stream order.  A plan must not be executed
+ * concurrently on two streams.
+ *
+ * Errors: functions returning int return FFT3D_OK (0) or a negative
+ * fft3d_status.  Plan constructors return NULL on error and record the code,
+ * readable with fft3d_last_error() (per host thread).  Argument checks run
+ * before any HIP call.
+ */
+#ifndef FFT3D_H
+#define FFT3D_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *fft3d_stream_t; /* the same type as hipStream_t */
+typedef struct fft3d_plan_s *fft3d_plan_t;   /* opaque */
+
+enum fft3d_precision {
+    FFT3D_FP32 = 0,        /* complex64 in, complex64 out, FP32 arithmetic */
+    FFT3D_FP16_SCALED = 1, /* scaled 16-bit storage, binary16 payload */
+    FFT3D_BF16_SCALED = 2  /* scaled 16-bit storage, bfloat16 payload */
+};
+
+enum fft3d_direction {
+    FFT3D_FORWARD = -1, /* exponent sign -1: Eq. (1) */
+    FFT3D_INVERSE = 1   /* exponent sign +1, unnormalised */
+};
+
+enum fft3d_status {
+    FFT3D_OK = 0,
+    FFT3D_E_INVALID_ARG = -1,      /* NULL plan/pointer, bad enum, batch < 1, size < 1 */
+    FFT3D_E_UNSUPPORTED_SIZE = -2, /* a dimension > 128 or not of the form 2^a 3^b 5^c */
+    FFT3D_E_NO_DEVICE = -3,        /* no usable HIP device */
+    FFT3D_E_ALLOC = -4,            /* device allocation failed at plan time */
+    FFT3D_E_LAUNCH = -5,           /* a kernel launch or HIP call failed */
+    FFT3D_E_ALIGNMENT = -6,        /* a data pointer is not 16-byte aligned */
+    FFT3D_E_UNSUPPORTED = -7       /* valid arguments, combination not provided */
+};
+
+/*
+ * Create a plan for `batch` grids of nx * ny * nz points (Section II, Eq. (1)).
+ * 1 <= nx, ny, nz <= 128, each 2^a 3^b 5^c; batch >= 1; precision one of
+ * fft3d_precision; direction FFT3D_FORWARD or FFT3D_INVERSE.  Builds the
+ * radix schedule, generates the twiddle factors in double precision (rounded
+ * once to the working precision) and uploads them to the current device.
+ * Returns NULL on error (see fft3d_last_error).
+ */
+fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int direction);
+
+/*
+ * Enqueue the transform of `in` into `out` on `stream`.  Both are device
+ * buffers of fft3d_buffer_bytes(plan) bytes.  in == out (in place) is
+ * allowed; out-of-place calls leave `in` unmodified.  Returns FFT3D_OK,
+ * FFT3D_E_INVALID_ARG (NULL plan or pointer), FFT3D_E_ALIGNMENT or
+ * FFT3D_E_LAUNCH.
+ */
+int fft3d_exec(fft3d_plan_t plan, const void *in, void *out, fft3d_stream_t stream);
+
+/* Release a plan and its device tables.  NULL is a no-op.  Returns FFT3D_OK. */
+int fft3d_destroy(fft3d_plan_t plan);
+
+/* Code of the last failed plan construction on this host thread (FFT3D_OK if none). */
+int fft3d_last_error(void);
+
+/* Static, human-readable text for a status code. */
+const char *fft3d_strerror(int code);
+
+/* Bytes of one input (and one output) buffer of the plan; 0 for NULL. */
+size_t fft3d_buffer_bytes(fft3d_plan_t plan);
+
+/*
+ * Write a one-line description of the plan's kernel schedule (kernels,
+ * radices, threads, LDS bytes) into buf (NUL-terminated, truncated to len).
+ * Returns the untruncated length, or a negative status.
+ */
+int fft3d_plan_describe(fft3d_plan_t plan, char *buf, size_t len);
+
+/*
+ * Measurement hooks.  An exec is a fixed sequence of kernel launches
+ * ("passes": e.g. the xy-plane pass and the z pass of Section II's
+ * decomposition).  fft3d_plan_passes returns how many; fft3d_exec_pass
+ * enqueues pass `pass` alone (0-based), reading `in` and writing `out`, so a
+ * profiler can time each kernel.  Running passes 0..k-1 in order with
+ * in -> out for pass 0 and out -> out afterwards is exactly fft3d_exec.
+ * Returns FFT3D_E_INVALID_ARG for a NULL plan/pointer or a pass out of range.
+ */
+int fft3d_plan_passes(fft3d_plan_t plan);
+int fft3d_exec_pass(fft3d_plan_t plan, int pass, const void *in, void *out, fft3d_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFT3D_H */

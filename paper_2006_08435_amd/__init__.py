@@ -1,0 +1,137 @@
+"""MI355X-native complex 3D FFT (the hot path of Ramaswami et al., Section II).
+
+Thin Python layer over the C ABI in ``include/fft3d.h`` (``libfft3d.so``):
+PyTorch supplies device memory and the current HIP stream; every step of the
+transform runs in the library's HIP kernels.
+
+    import paper_2006_08435_amd as fft3d
+    y = fft3d.fftn(x)        # x: complex64 CUDA tensor [B, Nz, Ny, Nx] or [Nz, Ny, Nx]
+    z = fft3d.ifftn(y)       # unnormalised: z == Nx*Ny*Nz * x
+"""
+from __future__ import annotations
+
+import threading
+
+from . import _lib
+from ._lib import (FFT3D_BF16_SCALED, FFT3D_FORWARD, FFT3D_FP16_SCALED, FFT3D_FP32,
+                   FFT3D_INVERSE, Fft3dError)
+
+PRECISIONS = {"fp32": FFT3D_FP32, "fp16": FFT3D_FP16_SCALED, "bf16": FFT3D_BF16_SCALED}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """A planned batch of nx*ny*nz transforms (owns its device tables)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, batch: int = 1, precision="fp32",
+                 direction: int = FFT3D_FORWARD):
+        lib = _lib.lib()
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = lib.fft3d_plan(int(nx), int(ny), int(nz), int(batch), prec, int(direction))
+        if not h:
+            raise Fft3dError(lib.fft3d_last_error(), "fft3d_plan(%d,%d,%d,%d)" % (nx, ny, nz, batch))
+        self._h = h
+        self.shape = (int(batch), int(nz), int(ny), int(nx))
+        self.precision = prec
+        self.direction = int(direction)
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    @property
+    def buffer_bytes(self) -> int:
+        return int(_lib.lib().fft3d_buffer_bytes(self._h))
+
+    def describe(self) -> str:
+        import ctypes
+        buf = ctypes.create_string_buffer(512)
+        _lib.lib().fft3d_plan_describe(self._h, buf, 512)
+        return buf.value.decode()
+
+    def exec_ptr(self, in_ptr: int, out_ptr: int, stream_handle: int) -> None:
+        _lib.check(_lib.lib().fft3d_exec(self._h, in_ptr, out_ptr, stream_handle), "fft3d_exec")
+
+    def exec(self, inp, out=None, stream=None):
+        """Transform device tensor ``inp`` into ``out`` (allocated if None)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(inp)
+        for t in (inp, out):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("tensors must be contiguous device tensors")
+            if t.numel() * t.element_size() != self.buffer_bytes:
+                raise ValueError("tensor holds %d bytes, plan needs %d"
+                                 % (t.numel() * t.element_size(), self.buffer_bytes))
+        self.exec_ptr(inp.data_ptr(), out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.lib().fft3d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_cache = {}
+_cache_lock = threading.Lock()
+
+
+def get_plan(nx, ny, nz, batch=1, precision="fp32", direction=FFT3D_FORWARD) -> Plan:
+    import torch
+    key = (nx, ny, nz, batch, precision, direction, torch.cuda.current_device())
+    with _cache_lock:
+        p = _cache.get(key)
+        if p is None:
+            p = Plan(nx, ny, nz, batch, precision, direction)
+            _cache[key] = p
+        return p
+
+
+def _as_batch(x):
+    if x.dim() == 3:
+        return x.unsqueeze(0), True
+    if x.dim() == 4:
+        return x, False
+    raise ValueError("expected [Nz,Ny,Nx] or [B,Nz,Ny,Nx], got %s" % (tuple(x.shape),))
+
+
+def _transform(x, direction, out=None):
+    torch = _torch()
+    if x.dtype != torch.complex64:
+        raise TypeError("fp32 path takes complex64 tensors")
+    xb, squeeze = _as_batch(x.contiguous())
+    b, nz, ny, nx = xb.shape
+    plan = get_plan(nx, ny, nz, b, "fp32", direction)
+    o = torch.empty_like(xb) if out is None else out.view(xb.shape)
+    plan.exec(xb, o)
+    return o[0] if squeeze else o
+
+
+def fftn(x, out=None):
+    """Eq. (1) over the last three axes (sign -1, unnormalised)."""
+    return _transform(x, FFT3D_FORWARD, out)
+
+
+def ifftn(x, out=None):
+    """Unnormalised inverse over the last three axes (sign +1)."""
+    return _transform(x, FFT3D_INVERSE, out)
+
+
+__all__ = ["Plan", "get_plan", "fftn", "ifftn", "Fft3dError", "FFT3D_FORWARD",
+           "FFT3D_INVERSE", "FFT3D_FP32", "FFT3D_FP16_SCALED", "FFT3D_BF16_SCALED"]

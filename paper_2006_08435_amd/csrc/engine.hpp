@@ -1,0 +1,138 @@
+// Workgroup-level engine for batches of 1D Stockham transforms.
+//
+// A workgroup holds a tile of L "lines" (independent 1D transforms of length
+// N).  Every stage of the radix schedule (sched.hpp) is one call of
+// fft_stage: each thread takes butterflies b = tid, tid + T, ...; reads its R
+// inputs through a source accessor, applies twiddles and the R-point DFT, and
+// writes its R outputs through a destination accessor.  Accessors map
+// (line, element) to an address, so the same stage code runs from global
+// memory into LDS, LDS to LDS, or LDS to global memory with any layout.
+//
+// Mapping of butterfly index b to (line, j):
+//   LINE_FAST: line = b mod L, j = b / L -- consecutive lanes take
+//              consecutive lines; used wherever consecutive lines are
+//              adjacent in memory (coalesced global access, conflict-free LDS
+//              with an odd line stride).  When L is a multiple of 64 every
+//              lane of a wave has the same j, so the twiddle index is
+//              wave-uniform and twiddles come through scalar loads.
+//   J_FAST:    j = b mod (N/R), line = b / (N/R).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "codelets.hpp"
+#include "sched.hpp"
+
+namespace fft3d {
+
+template <int N>
+struct Plan1D {
+    static constexpr Sched sc = make_sched(N);
+    static constexpr int stages = sc.count;
+    static constexpr int radix(int s) { return sc.r[s]; }
+    static constexpr int ns(int s) { return sched_ns(sc, s); }
+    static constexpr int tw_off(int s) { return sched_tw_off(sc, s); }
+    static constexpr int tw_len = sched_tw_len(sc);
+    static constexpr int max_radix = sched_max_radix(sc);
+    static constexpr int min_radix = sched_min_radix(sc);
+};
+
+// ---------------------------------------------------------------- accessors --
+
+// LDS tile: address = line * LS + e * ES (float2 units).
+template <int LS, int ES>
+struct LdsAcc {
+    float2* p;
+    __device__ __forceinline__ float2 load(int line, int e) const { return p[line * LS + e * ES]; }
+    __device__ __forceinline__ void store(int line, int e, float2 v) const { p[line * LS + e * ES] = v; }
+};
+
+// Global memory, line base offsets given per line by a functor-free form:
+// address = base + line * LS + e * ES (element units).
+template <long LS, long ES>
+struct GlobAcc {
+    const float2* src;
+    float2* dst;
+    __device__ __forceinline__ float2 load(int line, int e) const { return src[(long)line * LS + (long)e * ES]; }
+    __device__ __forceinline__ void store(int line, int e, float2 v) const { dst[(long)line * LS + (long)e * ES] = v; }
+};
+
+// Global memory with a runtime element stride and a per-thread line base
+// (the line index passed in is ignored; the caller has folded it into base).
+struct GlobStrided {
+    const float2* src;
+    float2* dst;
+    long es;
+    __device__ __forceinline__ float2 load(int, int e) const { return src[(long)e * es]; }
+    __device__ __forceinline__ void store(int, int e, float2 v) const { dst[(long)e * es] = v; }
+};
+
+// ------------------------------------------------------------------- stage --
+
+// One Stockham stage of the length-N schedule (stage index ST) over L lines
+// with T threads.  `valid(line)` masks lines beyond a ragged tile end.
+// SYNC: barrier between the read phase and the write phase (needed when
+// source and destination alias in LDS).
+template <int N, int ST, int S, int L, int T, bool LINE_FAST, bool SYNC, class Src, class Dst>
+__device__ __forceinline__ void fft_stage(const Src& src, const Dst& dst, const float2* __restrict__ tw,
+                                          int tid, int valid_lines = L)
+{
+    using P = Plan1D<N>;
+    constexpr int R = P::radix(ST);
+    constexpr int NS = P::ns(ST);
+    constexpr int M = N / R;
+    constexpr int NB = L * M;
+    constexpr int IT = (NB + T - 1) / T;
+    constexpr bool UNIFORM = LINE_FAST && (L % 64 == 0) && (T % 64 == 0);
+    const float2* __restrict__ tws = tw + P::tw_off(ST);
+
+    float2 v[IT][R];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int b = tid + it * T;
+        const int line = LINE_FAST ? b % L : b / M;
+        int j = LINE_FAST ? b / L : b % M;
+        if (UNIFORM) j = __builtin_amdgcn_readfirstlane(j);
+        if ((NB % T == 0 || b < NB) && line < valid_lines) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[it][q] = src.load(line, j + q * M);
+            if constexpr (NS > 1) {
+                const float2* __restrict__ w = tws + (j % NS) * (R - 1);
+#pragma unroll
+                for (int q = 1; q < R; ++q) v[it][q] = cmul(v[it][q], w[q - 1]);
+            }
+            dft<R, S>(v[it]);
+        }
+    }
+    if constexpr (SYNC) __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int b = tid + it * T;
+        const int line = LINE_FAST ? b % L : b / M;
+        const int j = LINE_FAST ? b / L : b % M;
+        if ((NB % T == 0 || b < NB) && line < valid_lines) {
+            const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+            for (int q = 0; q < R; ++q) dst.store(line, base + q * NS, v[it][q]);
+        }
+    }
+}
+
+// All stages of a length-N transform on an LDS tile, in place.
+// The tile is left in natural order; ends with a barrier.
+template <int N, int S, int L, int T, int LS, int ES>
+__device__ __forceinline__ void fft_lds_all(float2* lds, const float2* __restrict__ tw, int tid,
+                                            int valid_lines = L)
+{
+    using P = Plan1D<N>;
+    const LdsAcc<LS, ES> a{lds};
+    if constexpr (P::stages > 0) { fft_stage<N, 0, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (P::stages > 1) { fft_stage<N, 1, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (P::stages > 2) { fft_stage<N, 2, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (P::stages > 3) { fft_stage<N, 3, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (P::stages > 4) { fft_stage<N, 4, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (P::stages > 5) { fft_stage<N, 5, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (P::stages > 6) { fft_stage<N, 6, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (P::stages > 7) { fft_stage<N, 7, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
+}
+
+}  // namespace fft3d

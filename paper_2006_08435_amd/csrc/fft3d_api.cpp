@@ -1,0 +1,300 @@
+// Host side of libfft3d: argument validation, planning (schedule choice and
+// FP64 twiddle generation), and stream-ordered execution of the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fft3d.h"
+#include "kernels_fp32.hpp"
+#include "registry.hpp"
+#include "sched.hpp"
+
+using namespace fft3d;
+
+namespace {
+
+thread_local int g_last_error = FFT3D_OK;
+
+enum Scheme {
+    kCube = 0,    // whole grid per workgroup
+    kPlaneZ = 1,  // xy-plane pass + strided z pass (Nx == Ny)
+    kAxes = 2,    // x rows, strided y, strided z
+};
+
+int set_error(int code)
+{
+    g_last_error = code;
+    return code;
+}
+
+// Twiddle table of a length-n transform with exponent sign `sign`, in the
+// layout described in sched.hpp.  Angles are reduced to an integer index
+// modulo the root order before cos/sin (double precision), then rounded once
+// to float.
+std::vector<float2> twiddles(int n, int sign)
+{
+    const Sched sc = make_sched(n);
+    std::vector<float2> t(sched_tw_len(sc) > 0 ? sched_tw_len(sc) : 0);
+    for (int s = 1; s < sc.count; ++s) {
+        const int R = sc.r[s], NS = sched_ns(sc, s), order = NS * R;
+        const int off = sched_tw_off(sc, s);
+        for (int k = 0; k < NS; ++k)
+            for (int q = 1; q < R; ++q) {
+                const long m = ((long)k * q) % order;
+                const double a = 2.0 * M_PI * (double)m / (double)order;
+                t[off + k * (R - 1) + (q - 1)] = make_float2((float)std::cos(a), (float)(sign * std::sin(a)));
+            }
+    }
+    return t;
+}
+
+bool test_fail_alloc()
+{
+    const char* e = std::getenv("FFT3D_TEST_FAIL_ALLOC");
+    return e && e[0] == '1';
+}
+
+}  // namespace
+
+namespace {
+
+// One kernel launch of an exec.  The first pass reads the caller's input,
+// every later pass works in place on the output buffer.
+struct Pass {
+    enum Kind { kCubeK, kPlaneK, kRowK, kStrK } kind;
+    int n;        // transform length of this pass
+    long count;   // grids / planes / rows (cube, plane, row kinds)
+    AxisMap map;  // strided kind
+    long tw;      // offset of this pass's twiddle table in d_tw
+};
+
+}  // namespace
+
+struct fft3d_plan_s {
+    int nx, ny, nz, batch, precision, direction;
+    int scheme;
+    int device;
+    float2* d_tw;           // all tables of the plan, one allocation
+    long tw_x, tw_y, tw_z;  // offsets (elements) of each dimension's table
+    long vol;
+    std::vector<Pass> passes;
+};
+
+extern "C" {
+
+const char* fft3d_strerror(int code)
+{
+    switch (code) {
+    case FFT3D_OK: return "success";
+    case FFT3D_E_INVALID_ARG: return "invalid argument";
+    case FFT3D_E_UNSUPPORTED_SIZE: return "unsupported size (each dimension must be 2^a 3^b 5^c, 1..128)";
+    case FFT3D_E_NO_DEVICE: return "no usable HIP device";
+    case FFT3D_E_ALLOC: return "device allocation failed";
+    case FFT3D_E_LAUNCH: return "kernel launch or HIP call failed";
+    case FFT3D_E_ALIGNMENT: return "data pointer not 16-byte aligned";
+    case FFT3D_E_UNSUPPORTED: return "valid arguments, combination not provided";
+    default: return "unknown status";
+    }
+}
+
+int fft3d_last_error(void) { return g_last_error; }
+
+fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int direction)
+{
+    g_last_error = FFT3D_OK;
+    if (nx < 1 || ny < 1 || nz < 1 || batch < 1) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
+    if (precision != FFT3D_FP32 && precision != FFT3D_FP16_SCALED && precision != FFT3D_BF16_SCALED) {
+        set_error(FFT3D_E_INVALID_ARG);
+        return nullptr;
+    }
+    if (direction != FFT3D_FORWARD && direction != FFT3D_INVERSE) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
+    if (!size_supported(nx) || !size_supported(ny) || !size_supported(nz)) {
+        set_error(FFT3D_E_UNSUPPORTED_SIZE);
+        return nullptr;
+    }
+    const long vol = (long)nx * ny * nz;
+    // 2^36 points (512 GiB of complex64) bounds every grid dimension of every
+    // launch below 2^31 workgroups.
+    if ((long)batch * vol > (1L << 36)) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
+    if (precision != FFT3D_FP32) { set_error(FFT3D_E_UNSUPPORTED); return nullptr; }
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        set_error(FFT3D_E_NO_DEVICE);
+        return nullptr;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { set_error(FFT3D_E_NO_DEVICE); return nullptr; }
+
+    fft3d_plan_s* p = new (std::nothrow) fft3d_plan_s{};
+    if (!p) { set_error(FFT3D_E_ALLOC); return nullptr; }
+    p->nx = nx; p->ny = ny; p->nz = nz; p->batch = batch;
+    p->precision = precision; p->direction = direction; p->device = dev; p->vol = vol;
+    if (nx == ny && ny == nz && nx <= kCubeMaxN) p->scheme = kCube;
+    else if (nx == ny) p->scheme = kPlaneZ;
+    else p->scheme = kAxes;
+
+    // One table per dimension (identical lengths share nothing on purpose:
+    // the tables are tiny and separate offsets keep the exec path simple).
+    std::vector<float2> tab;
+    auto append = [&](int n) {
+        const long off = (long)tab.size();
+        std::vector<float2> t = twiddles(n, direction);
+        tab.insert(tab.end(), t.begin(), t.end());
+        // keep every table 16-byte aligned
+        if (tab.size() % 2) tab.push_back(make_float2(0.f, 0.f));
+        return off;
+    };
+    p->tw_x = append(nx);
+    p->tw_y = append(ny);
+    p->tw_z = append(nz);
+    if (tab.empty()) tab.push_back(make_float2(0.f, 0.f));
+    const size_t bytes = tab.size() * sizeof(float2);
+    if (test_fail_alloc() || hipMalloc((void**)&p->d_tw, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        set_error(FFT3D_E_ALLOC);
+        return nullptr;
+    }
+    if (hipMemcpy(p->d_tw, tab.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(p->d_tw);
+        delete p;
+        set_error(FFT3D_E_LAUNCH);
+        return nullptr;
+    }
+    const long B = batch;
+    const AxisMap zmap{B * ny * nx, nx, ny, vol, (long)nx, (long)nx * ny};
+    const AxisMap ymap{B * nz * nx, nx, nz, vol, (long)nx * ny, (long)nx};
+    if (p->scheme == kCube) {
+        p->passes.push_back({Pass::kCubeK, nx, B, {}, p->tw_x});
+    } else if (p->scheme == kPlaneZ) {
+        p->passes.push_back({Pass::kPlaneK, nx, B * nz, {}, p->tw_x});
+        if (nz > 1) p->passes.push_back({Pass::kStrK, nz, 0, zmap, p->tw_z});
+    } else {
+        if (nx > 1) p->passes.push_back({Pass::kRowK, nx, B * nz * ny, {}, p->tw_x});
+        if (ny > 1) p->passes.push_back({Pass::kStrK, ny, 0, ymap, p->tw_y});
+        if (nz > 1) p->passes.push_back({Pass::kStrK, nz, 0, zmap, p->tw_z});
+    }
+    return p;
+}
+
+int fft3d_destroy(fft3d_plan_t p)
+{
+    if (!p) return FFT3D_OK;
+    if (p->d_tw) (void)hipFree(p->d_tw);
+    delete p;
+    return FFT3D_OK;
+}
+
+size_t fft3d_buffer_bytes(fft3d_plan_t p)
+{
+    if (!p) return 0;
+    return (size_t)p->batch * (size_t)p->vol * sizeof(float2);
+}
+
+static hipError_t run_pass(const fft3d_plan_s* p, const Pass& ps, const float2* src, float2* dst,
+                           hipStream_t st)
+{
+    const int S = p->direction;
+    const float2* tw = p->d_tw + ps.tw;
+    switch (ps.kind) {
+    case Pass::kCubeK: return cube_fn(ps.n, S)(src, dst, tw, ps.count, st);
+    case Pass::kPlaneK: return plane_fn(ps.n, S)(src, dst, tw, ps.count, st);
+    case Pass::kRowK: return axis_row_fn(ps.n, S)(src, dst, tw, ps.count, st);
+    case Pass::kStrK: return axis_str_fn(ps.n, S)(src, dst, tw, ps.map, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+static int check_ptrs(fft3d_plan_t p, const void* in, const void* out)
+{
+    if (!p || !in || !out) return FFT3D_E_INVALID_ARG;
+    if (((uintptr_t)in % 16) || ((uintptr_t)out % 16)) return FFT3D_E_ALIGNMENT;
+    return FFT3D_OK;
+}
+
+int fft3d_exec(fft3d_plan_t p, const void* in, void* out, fft3d_stream_t stream)
+{
+    const int rc = check_ptrs(p, in, out);
+    if (rc != FFT3D_OK) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const float2* src = static_cast<const float2*>(in);
+    float2* dst = static_cast<float2*>(out);
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < p->passes.size() && e == hipSuccess; ++i)
+        e = run_pass(p, p->passes[i], i == 0 ? src : dst, dst, st);
+    if (e == hipSuccess && p->passes.empty() && src != dst)
+        e = hipMemcpyAsync(dst, src, fft3d_buffer_bytes(p), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
+int fft3d_plan_passes(fft3d_plan_t p)
+{
+    if (!p) return FFT3D_E_INVALID_ARG;
+    return (int)p->passes.size();
+}
+
+int fft3d_exec_pass(fft3d_plan_t p, int pass, const void* in, void* out, fft3d_stream_t stream)
+{
+    const int rc = check_ptrs(p, in, out);
+    if (rc != FFT3D_OK) return rc;
+    if (pass < 0 || pass >= (int)p->passes.size()) return FFT3D_E_INVALID_ARG;
+    const hipError_t e = run_pass(p, p->passes[pass], static_cast<const float2*>(in), static_cast<float2*>(out),
+                                  reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
+int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
+{
+    if (!p) return FFT3D_E_INVALID_ARG;
+    auto radices = [](int n) {
+        const Sched sc = make_sched(n);
+        std::string s;
+        for (int i = 0; i < sc.count; ++i) s += (i ? "x" : "") + std::to_string(sc.r[i]);
+        return s;
+    };
+    std::string d;
+    char tmp[256];
+    if (p->scheme == kCube) {
+        const KernelInfo k = cube_info(p->nx);
+        snprintf(tmp, sizeof tmp, "cube n=%d radices=%s threads=%d lds=%d grids=%d", p->nx,
+                 radices(p->nx).c_str(), k.threads, k.lds_bytes, p->batch);
+        d = tmp;
+    } else if (p->scheme == kPlaneZ) {
+        const KernelInfo a = plane_info(p->nx), b = axis_str_info(p->nz);
+        snprintf(tmp, sizeof tmp, "plane n=%d radices=%s threads=%d lds=%d planes=%ld; z n=%d radices=%s threads=%d lds=%d",
+                 p->nx, radices(p->nx).c_str(), a.threads, a.lds_bytes, (long)p->batch * p->nz, p->nz,
+                 radices(p->nz).c_str(), b.threads, b.lds_bytes);
+        d = tmp;
+    } else {
+        const KernelInfo a = axis_row_info(p->nx), b = axis_str_info(p->ny), c = axis_str_info(p->nz);
+        snprintf(tmp, sizeof tmp, "axes x=%d(%s,t%d) y=%d(%s,t%d) z=%d(%s,t%d)", p->nx, radices(p->nx).c_str(),
+                 a.threads, p->ny, radices(p->ny).c_str(), b.threads, p->nz, radices(p->nz).c_str(), c.threads);
+        d = tmp;
+    }
+    d += p->direction < 0 ? " forward" : " inverse";
+    if (buf && len) {
+        std::strncpy(buf, d.c_str(), len - 1);
+        buf[len - 1] = 0;
+    }
+    return (int)d.size();
+}
+
+}  // extern "C"

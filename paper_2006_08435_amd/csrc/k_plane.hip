@@ -1,0 +1,37 @@
+// xy-plane (pass A) kernel instances, Nx = Ny = N for every supported N.
+#include "kernels_fp32.hpp"
+#include "registry.hpp"
+
+namespace fft3d {
+
+template <int N, int S>
+static hipError_t launch_plane(const float2* in, float2* out, const float2* tw, long planes, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_plane<N, S>), dim3((unsigned)planes), dim3(PlaneGeom<N>::T), 0, st, in, out, tw);
+    return hipGetLastError();
+}
+
+#define FFT3D_PLANE_CASE(n)                                                    \
+    case n:                                                                    \
+        return sign < 0 ? &launch_plane<n, -1> : &launch_plane<n, 1>;
+#define FFT3D_PLANE_INFO(n)                                                    \
+    case n:                                                                    \
+        return {PlaneGeom<n>::T, (int)(PlaneGeom<n>::WORDS * sizeof(float2))};
+
+PlaneFn plane_fn(int n, int sign)
+{
+    switch (n) {
+        FFT3D_FOR_EACH_SIZE(FFT3D_PLANE_CASE)
+    default: return nullptr;
+    }
+}
+
+KernelInfo plane_info(int n)
+{
+    switch (n) {
+        FFT3D_FOR_EACH_SIZE(FFT3D_PLANE_INFO)
+    default: return {0, 0};
+    }
+}
+
+}  // namespace fft3d

@@ -1,0 +1,97 @@
+// Radix schedules and twiddle-table geometry shared by the host planner and
+// the device kernels of the FP32 path.
+//
+// A 1D transform of length N (2*3*5-smooth, 1 <= N <= 128) is computed as a
+// sequence of self-sorting (Stockham) radix-R stages.  Stage s has radix r[s]
+// and "span" NS(s) = r[0] * ... * r[s-1]; its butterfly j reads elements
+// j + q*N/R (q < R), multiplies element q by W_{NS*R}^{(j mod NS) q}, applies
+// the R-point DFT and writes element (j / NS) * NS * R + (j mod NS) + q * NS.
+// After the last stage the result is in natural order.
+//
+// Twiddle table of a length-N transform and sign S: for every stage s >= 1,
+// NS(s) * (R - 1) complex values tw[off(s) + k * (R - 1) + (q - 1)] =
+// exp(S * 2 pi i * k q / (NS(s) * R)), k < NS(s), 1 <= q < R.
+#pragma once
+
+namespace fft3d {
+
+struct Sched {
+    int count;
+    int r[8];
+};
+
+__host__ __device__ constexpr Sched make_sched(int n)
+{
+    Sched s{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+    if (n == 1) {
+        s.r[s.count++] = 1;
+        return s;
+    }
+    int m = n, p2 = 0;
+    while (m % 2 == 0) { m /= 2; ++p2; }
+    switch (p2) {
+    case 0: break;
+    case 1: s.r[s.count++] = 2; break;
+    case 2: s.r[s.count++] = 4; break;
+    case 3: s.r[s.count++] = 8; break;
+    case 4: s.r[s.count++] = 16; break;
+    case 5: s.r[s.count++] = 8; s.r[s.count++] = 4; break;
+    case 6: s.r[s.count++] = 8; s.r[s.count++] = 8; break;
+    default: s.r[s.count++] = 8; s.r[s.count++] = 16; break;   // 128
+    }
+    while (m % 3 == 0) { s.r[s.count++] = 3; m /= 3; }
+    while (m % 5 == 0) { s.r[s.count++] = 5; m /= 5; }
+    return s;
+}
+
+__host__ __device__ constexpr int sched_ns(const Sched& s, int stage)
+{
+    int p = 1;
+    for (int i = 0; i < stage; ++i) p *= s.r[i];
+    return p;
+}
+
+__host__ __device__ constexpr int sched_tw_off(const Sched& s, int stage)
+{
+    int o = 0;
+    for (int i = 1; i < stage; ++i) o += sched_ns(s, i) * (s.r[i] - 1);
+    return o;
+}
+
+__host__ __device__ constexpr int sched_tw_len(const Sched& s)
+{
+    return sched_tw_off(s, s.count);
+}
+
+__host__ __device__ constexpr int sched_max_radix(const Sched& s)
+{
+    int m = 1;
+    for (int i = 0; i < s.count; ++i) m = s.r[i] > m ? s.r[i] : m;
+    return m;
+}
+
+__host__ __device__ constexpr int sched_min_radix(const Sched& s)
+{
+    int m = 1 << 30;
+    for (int i = 0; i < s.count; ++i) m = s.r[i] < m ? s.r[i] : m;
+    return m;
+}
+
+// Supported lengths: 2*3*5-smooth, 1..128.
+__host__ __device__ constexpr bool size_supported(int n)
+{
+    if (n < 1 || n > 128) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    while (n % 5 == 0) n /= 5;
+    return n == 1;
+}
+
+}  // namespace fft3d
+
+// X-macro over every supported length.
+#define FFT3D_FOR_EACH_SIZE(X)                                                 \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(18)      \
+    X(20) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(45) X(48) X(50) X(54)    \
+    X(60) X(64) X(72) X(75) X(80) X(81) X(90) X(96) X(100) X(108) X(120)       \
+    X(125) X(128)

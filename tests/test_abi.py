@@ -1,0 +1,89 @@
+"""The C ABI: exported symbols and host-side argument checks (CPU, no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER_DIR = os.path.join(ROOT, "include")
+
+
+def _lib():
+    from paper_2006_08435_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return _lib
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(HEADER_DIR):
+        if fn.endswith(".h"):
+            text = open(os.path.join(HEADER_DIR, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(fft3d_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib()
+    names = declared_functions()
+    assert "fft3d_plan" in names and "fft3d_exec" in names
+    raw = ctypes.CDLL(L.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(raw, n), "missing export " + n
+    # and the binding knows every declared function
+    assert names <= set(L.SIGNATURES), names - set(L.SIGNATURES)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 16, 16, 1, 0, -1), -1), ((-1, 16, 16, 1, 0, -1), -1), ((16, 16, 16, 0, 0, -1), -1),
+    ((16, 16, 16, -3, 0, -1), -1), ((16, 16, 16, 1, 3, -1), -1), ((16, 16, 16, 1, -1, -1), -1),
+    ((16, 16, 16, 1, 0, 0), -1), ((16, 16, 16, 1, 0, 2), -1),
+    ((7, 16, 16, 1, 0, -1), -2), ((16, 11, 16, 1, 0, -1), -2), ((16, 16, 129, 1, 0, -1), -2),
+    ((256, 16, 16, 1, 0, -1), -2), ((14, 16, 16, 1, 0, -1), -2),
+])
+def test_plan_rejects_bad_arguments(args, code):
+    L = _lib()
+    lib = L.lib()
+    assert not lib.fft3d_plan(*args)
+    assert lib.fft3d_last_error() == code
+
+
+def test_null_handles():
+    lib = _lib().lib()
+    assert lib.fft3d_destroy(None) == 0
+    assert lib.fft3d_buffer_bytes(None) == 0
+    assert lib.fft3d_exec(None, None, None, None) == -1
+    assert lib.fft3d_plan_describe(None, None, 0) == -1
+
+
+def test_strerror_covers_codes():
+    lib = _lib().lib()
+    seen = set()
+    for c in range(0, -8, -1):
+        s = lib.fft3d_strerror(c).decode()
+        assert s and s != "unknown status"
+        seen.add(s)
+    assert len(seen) == 8
+    assert lib.fft3d_strerror(-99).decode() == "unknown status"
+
+
+def test_no_device_reported_on_cpu_host():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = _lib().lib()
+    assert not lib.fft3d_plan(16, 16, 16, 1, 0, -1)
+    assert lib.fft3d_last_error() == -3
+
+
+def test_python_layer_raises_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_2006_08435_amd as fft3d
+    with pytest.raises(fft3d.Fft3dError):
+        fft3d.Plan(16, 16, 16)
