@@ -66,7 +66,8 @@ enum fft3d_status {
     FFT3D_E_ALLOC = -4,            /* device allocation failed at plan time */
     FFT3D_E_LAUNCH = -5,           /* a kernel launch or HIP call failed */
     FFT3D_E_ALIGNMENT = -6,        /* a data pointer is not 16-byte aligned */
-    FFT3D_E_UNSUPPORTED = -7       /* valid arguments, combination not provided */
+    FFT3D_E_UNSUPPORTED = -7,      /* valid arguments, combination not provided */
+    FFT3D_E_TIMEOUT = -8           /* a bounded in-kernel wait expired (see fft3d_plan_check) */
 };
 
 /*
@@ -117,6 +118,15 @@ int fft3d_plan_describe(fft3d_plan_t plan, char *buf, size_t len);
  * Returns FFT3D_E_INVALID_ARG for a NULL plan/pointer or a pass out of range.
  */
 int fft3d_plan_passes(fft3d_plan_t plan);
+/*
+ * Health check of a plan's device-side state.  Batches of cubic grids run as
+ * one persistent kernel in which the z pass of a grid waits, with a bounded
+ * spin, for that grid's xy-plane pass; if any such wait ever expired (which
+ * would mean an invalid result) this returns FFT3D_E_TIMEOUT once and clears
+ * the flag.  Synchronises the device: for tests and diagnostics, not for the
+ * hot path.  Returns FFT3D_OK, FFT3D_E_INVALID_ARG or FFT3D_E_LAUNCH.
+ */
+int fft3d_plan_check(fft3d_plan_t plan);
 int fft3d_exec_pass(fft3d_plan_t plan, int pass, const void *in, void *out, fft3d_stream_t stream);
 
 #ifdef __cplusplus

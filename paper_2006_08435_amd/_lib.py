@@ -20,6 +20,7 @@ FFT3D_E_ALLOC = -4
 FFT3D_E_LAUNCH = -5
 FFT3D_E_ALIGNMENT = -6
 FFT3D_E_UNSUPPORTED = -7
+FFT3D_E_TIMEOUT = -8
 
 FFT3D_FP32 = 0
 FFT3D_FP16_SCALED = 1
@@ -39,6 +40,7 @@ SIGNATURES = {
     "fft3d_buffer_bytes": (ctypes.c_size_t, [_vp]),
     "fft3d_plan_describe": (_ci, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "fft3d_plan_passes": (_ci, [_vp]),
+    "fft3d_plan_check": (_ci, [_vp]),
     "fft3d_exec_pass": (_ci, [_vp, _ci, _vp, _vp, _vp]),
 }
 

@@ -66,6 +66,38 @@ struct GlobStrided {
     __device__ __forceinline__ void store(int, int e, float2 v) const { dst[(long)e * es] = v; }
 };
 
+// Device-coherent 8-byte global accesses: the load misses every cache that
+// is not coherent across the device's L2 slices and the store writes through
+// them (agent-scope relaxed atomics, i.e. sc1 accesses on gfx950).  Used for
+// data handed from one workgroup to another inside one kernel launch.
+__device__ __forceinline__ float2 load_coherent(const float2* p)
+{
+    const unsigned long long b = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(float2, b);
+}
+__device__ __forceinline__ void store_coherent(float2* p, float2 v)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Global memory, lines adjacent (line stride 1), runtime element stride;
+// COH_LOAD selects device-coherent loads.
+template <bool COH_LOAD = false>
+struct GlobLines {
+    const float2* src;
+    float2* dst;
+    long es;
+    __device__ __forceinline__ float2 load(int line, int e) const
+    {
+        const float2* p = src + line + (long)e * es;
+        if constexpr (COH_LOAD) return load_coherent(p);
+        else return *p;
+    }
+    __device__ __forceinline__ void store(int line, int e, float2 v) const { dst[line + (long)e * es] = v; }
+};
+
 // ------------------------------------------------------------------- stage --
 
 // One Stockham stage of the length-N schedule (stage index ST) over L lines

@@ -26,6 +26,7 @@ enum Scheme {
     kCube = 0,    // whole grid per workgroup
     kPlaneZ = 1,  // xy-plane pass + strided z pass (Nx == Ny)
     kAxes = 2,    // x rows, strided y, strided z
+    kFused = 3,   // persistent plane + z-slab kernel (cubic)
 };
 
 int set_error(int code)
@@ -55,11 +56,13 @@ std::vector<float2> twiddles(int n, int sign)
     return t;
 }
 
-bool test_fail_alloc()
+bool env_flag(const char* name)
 {
-    const char* e = std::getenv("FFT3D_TEST_FAIL_ALLOC");
+    const char* e = std::getenv(name);
     return e && e[0] == '1';
 }
+
+bool test_fail_alloc() { return env_flag("FFT3D_TEST_FAIL_ALLOC"); }
 
 }  // namespace
 
@@ -68,11 +71,12 @@ namespace {
 // One kernel launch of an exec.  The first pass reads the caller's input,
 // every later pass works in place on the output buffer.
 struct Pass {
-    enum Kind { kCubeK, kPlaneK, kRowK, kStrK } kind;
+    enum Kind { kCubeK, kPlaneK, kPlanePfK, kRowK, kStrK, kFusedK } kind;
     int n;        // transform length of this pass
     long count;   // grids / planes / rows (cube, plane, row kinds)
     AxisMap map;  // strided kind
     long tw;      // offset of this pass's twiddle table in d_tw
+    int grid;     // workgroups of a persistent launch
 };
 
 }  // namespace
@@ -85,6 +89,10 @@ struct fft3d_plan_s {
     long tw_x, tw_y, tw_z;  // offsets (elements) of each dimension's table
     long vol;
     std::vector<Pass> passes;
+    FusedCtl* ctl;   // persistent-kernel control block (kFused)
+    int fused_grid;  // workgroups of the persistent launch
+    int fused_lag;   // dependency lag in grids
+    int fused_chunk; // items per queue claim (0: static round robin)
 };
 
 extern "C" {
@@ -100,6 +108,7 @@ const char* fft3d_strerror(int code)
     case FFT3D_E_LAUNCH: return "kernel launch or HIP call failed";
     case FFT3D_E_ALIGNMENT: return "data pointer not 16-byte aligned";
     case FFT3D_E_UNSUPPORTED: return "valid arguments, combination not provided";
+    case FFT3D_E_TIMEOUT: return "a bounded in-kernel wait expired (result invalid)";
     default: return "unknown status";
     }
 }
@@ -139,6 +148,7 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
     p->nx = nx; p->ny = ny; p->nz = nz; p->batch = batch;
     p->precision = precision; p->direction = direction; p->device = dev; p->vol = vol;
     if (nx == ny && ny == nz && nx <= kCubeMaxN) p->scheme = kCube;
+    else if (nx == ny && ny == nz && fused_fn(nx, direction) && env_flag("FFT3D_FUSED")) p->scheme = kFused;
     else if (nx == ny) p->scheme = kPlaneZ;
     else p->scheme = kAxes;
 
@@ -174,10 +184,38 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
     const long B = batch;
     const AxisMap zmap{B * ny * nx, nx, ny, vol, (long)nx, (long)nx * ny};
     const AxisMap ymap{B * nz * nx, nx, nz, vol, (long)nx * ny, (long)nx};
-    if (p->scheme == kCube) {
+    if (p->scheme == kFused) {
+        const size_t cb = sizeof(FusedCtl) + sizeof(unsigned) * (size_t)batch;
+        if (hipMalloc((void**)&p->ctl, cb) != hipSuccess || hipMemset(p->ctl, 0, cb) != hipSuccess) {
+            (void)hipGetLastError();
+            if (p->ctl) (void)hipFree(p->ctl);
+            (void)hipFree(p->d_tw);
+            delete p;
+            set_error(FFT3D_E_ALLOC);
+            return nullptr;
+        }
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+        const int resident = fused_blocks_per_cu(nx) * cus;
+        const long items = 2L * batch * nx;
+        p->fused_grid = (int)(items < resident ? items : resident);
+        p->fused_lag = (resident + nx - 1) / nx + 1;
+        const char* ck = std::getenv("FFT3D_FUSED_CHUNK");
+        p->fused_chunk = ck ? std::atoi(ck) : 1;
+        p->passes.push_back({Pass::kFusedK, nx, B, {}, p->tw_x});
+    } else if (p->scheme == kCube) {
         p->passes.push_back({Pass::kCubeK, nx, B, {}, p->tw_x});
     } else if (p->scheme == kPlaneZ) {
-        p->passes.push_back({Pass::kPlaneK, nx, B * nz, {}, p->tw_x});
+        if (plane_pf_fn(nx, direction) && !env_flag("FFT3D_NO_PLANE_PF")) {
+            int cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+                cus = 1;
+            const long resident = (long)plane_pf_blocks_per_cu(nx) * cus;
+            const long planes = B * nz;
+            p->passes.push_back({Pass::kPlanePfK, nx, planes, {}, p->tw_x, (int)(planes < resident ? planes : resident)});
+        } else {
+            p->passes.push_back({Pass::kPlaneK, nx, B * nz, {}, p->tw_x});
+        }
         if (nz > 1) p->passes.push_back({Pass::kStrK, nz, 0, zmap, p->tw_z});
     } else {
         if (nx > 1) p->passes.push_back({Pass::kRowK, nx, B * nz * ny, {}, p->tw_x});
@@ -191,6 +229,7 @@ int fft3d_destroy(fft3d_plan_t p)
 {
     if (!p) return FFT3D_OK;
     if (p->d_tw) (void)hipFree(p->d_tw);
+    if (p->ctl) (void)hipFree(p->ctl);
     delete p;
     return FFT3D_OK;
 }
@@ -209,8 +248,11 @@ static hipError_t run_pass(const fft3d_plan_s* p, const Pass& ps, const float2* 
     switch (ps.kind) {
     case Pass::kCubeK: return cube_fn(ps.n, S)(src, dst, tw, ps.count, st);
     case Pass::kPlaneK: return plane_fn(ps.n, S)(src, dst, tw, ps.count, st);
+    case Pass::kPlanePfK: return plane_pf_fn(ps.n, S)(src, dst, tw, ps.count, ps.grid, st);
     case Pass::kRowK: return axis_row_fn(ps.n, S)(src, dst, tw, ps.count, st);
     case Pass::kStrK: return axis_str_fn(ps.n, S)(src, dst, tw, ps.map, st);
+    case Pass::kFusedK:
+        return fused_fn(ps.n, S)(src, dst, tw, p->ctl, p->batch, p->fused_lag, p->fused_grid, p->fused_chunk, st);
     }
     return hipErrorInvalidValue;
 }
@@ -261,6 +303,24 @@ int fft3d_exec_pass(fft3d_plan_t p, int pass, const void* in, void* out, fft3d_s
     return FFT3D_OK;
 }
 
+int fft3d_plan_check(fft3d_plan_t p)
+{
+    if (!p) return FFT3D_E_INVALID_ARG;
+    if (!p->ctl) return FFT3D_OK;
+    unsigned t = 0;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&t, &p->ctl->timeouts, sizeof t, hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    if (t) {
+        const unsigned z = 0;
+        (void)hipMemcpy(&p->ctl->timeouts, &z, sizeof z, hipMemcpyHostToDevice);
+        return FFT3D_E_TIMEOUT;
+    }
+    return FFT3D_OK;
+}
+
 int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
 {
     if (!p) return FFT3D_E_INVALID_ARG;
@@ -272,7 +332,12 @@ int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
     };
     std::string d;
     char tmp[256];
-    if (p->scheme == kCube) {
+    if (p->scheme == kFused) {
+        const KernelInfo k = fused_info(p->nx);
+        snprintf(tmp, sizeof tmp, "fused n=%d radices=%s threads=%d lds=%d grids=%d workgroups=%d lag=%d", p->nx,
+                 radices(p->nx).c_str(), k.threads, k.lds_bytes, p->batch, p->fused_grid, p->fused_lag);
+        d = tmp;
+    } else if (p->scheme == kCube) {
         const KernelInfo k = cube_info(p->nx);
         snprintf(tmp, sizeof tmp, "cube n=%d radices=%s threads=%d lds=%d grids=%d", p->nx,
                  radices(p->nx).c_str(), k.threads, k.lds_bytes, p->batch);
@@ -290,6 +355,11 @@ int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
         d = tmp;
     }
     d += p->direction < 0 ? " forward" : " inverse";
+    d += " kernels=";
+    for (size_t i = 0; i < p->passes.size(); ++i) {
+        static const char* names[] = {"k_cube", "k_plane", "k_plane_pf", "k_axis_row", "k_axis_str", "k_fused"};
+        d += (i ? "," : "") + std::string(names[p->passes[i].kind]);
+    }
     if (buf && len) {
         std::strncpy(buf, d.c_str(), len - 1);
         buf[len - 1] = 0;

@@ -11,6 +11,49 @@ static hipError_t launch_plane(const float2* in, float2* out, const float2* tw, 
     return hipGetLastError();
 }
 
+template <int N, int S>
+static hipError_t launch_plane_pf(const float2* in, float2* out, const float2* tw, long planes, int grid,
+                                  hipStream_t st)
+{
+    hipLaunchKernelGGL((k_plane_pf<N, S>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out, tw, planes);
+    return hipGetLastError();
+}
+
+template <int N>
+static int plane_pf_occ()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_plane_pf<N, -1>),
+                                                     PlaneGeom<N>::T, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return nb > 0 ? nb : 1;
+}
+
+#define FFT3D_PLANE_PF_CASE(n)                                                 \
+    case n:                                                                    \
+        return sign < 0 ? &launch_plane_pf<n, -1> : &launch_plane_pf<n, 1>;
+#define FFT3D_PLANE_PF_OCC(n)                                                  \
+    case n:                                                                    \
+        return plane_pf_occ<n>();
+
+PlanePfFn plane_pf_fn(int n, int sign)
+{
+    switch (n) {
+        FFT3D_FOR_EACH_FUSED_SIZE(FFT3D_PLANE_PF_CASE)
+    default: return nullptr;
+    }
+}
+
+int plane_pf_blocks_per_cu(int n)
+{
+    switch (n) {
+        FFT3D_FOR_EACH_FUSED_SIZE(FFT3D_PLANE_PF_OCC)
+    default: return 1;
+    }
+}
+
 #define FFT3D_PLANE_CASE(n)                                                    \
     case n:                                                                    \
         return sign < 0 ? &launch_plane<n, -1> : &launch_plane<n, 1>;

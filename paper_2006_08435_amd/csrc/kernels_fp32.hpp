@@ -15,6 +15,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "engine.hpp"
 
 namespace fft3d {
@@ -65,6 +67,126 @@ __device__ __forceinline__ void run_tail(const A& a, const D& last, const float2
     }
 }
 
+// Copy a contiguous run of ROWS * ROW complex values between global memory
+// and an LDS tile with row stride RS, all loads issued before any LDS store
+// (and all LDS reads before any global store).  Even-length rows move as
+// 16-byte pairs.  `rows` <= ROWS masks a ragged tail.
+template <int ROWS, int ROW, int RS, int T>
+__device__ __forceinline__ void tile_to_lds(const float2* g, float2* lds, int tid, int rows = ROWS)
+{
+    if constexpr (ROW % 2 == 0) {
+        constexpr int PAIRS = ROWS * ROW / 2, IT = (PAIRS + T - 1) / T;
+        const float4* g4 = reinterpret_cast<const float4*>(g);
+        float4 r[IT];
+        const int lim = rows * ROW / 2;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (i < lim) r[k] = g4[i];
+        }
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (i < lim) {
+                const int e = 2 * i, row = e / ROW, col = e % ROW;
+                lds[row * RS + col] = make_float2(r[k].x, r[k].y);
+                lds[row * RS + col + 1] = make_float2(r[k].z, r[k].w);
+            }
+        }
+    } else {
+        constexpr int E = ROWS * ROW, IT = (E + T - 1) / T;
+        float2 r[IT];
+        const int lim = rows * ROW;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (i < lim) r[k] = g[i];
+        }
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (i < lim) lds[(i / ROW) * RS + (i % ROW)] = r[k];
+        }
+    }
+}
+
+// The same copy split in two halves so the global loads of the next tile can
+// be in flight while the current tile is being transformed.
+template <int ROWS, int ROW, int T>
+struct TileRegs {
+    static constexpr bool PAIRS = ROW % 2 == 0;
+    static constexpr int UNITS = PAIRS ? ROWS * ROW / 2 : ROWS * ROW;
+    static constexpr int IT = (UNITS + T - 1) / T;
+    using U = typename std::conditional<PAIRS, float4, float2>::type;
+    U r[IT];
+
+    __device__ __forceinline__ void load(const float2* g, int tid)
+    {
+        const U* gu = reinterpret_cast<const U*>(g);
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (UNITS % T == 0 || i < UNITS) r[k] = gu[i];
+        }
+    }
+    template <int RS>
+    __device__ __forceinline__ void store_lds(float2* lds, int tid) const
+    {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (UNITS % T == 0 || i < UNITS) {
+                if constexpr (PAIRS) {
+                    const int e = 2 * i, row = e / ROW, col = e % ROW;
+                    lds[row * RS + col] = make_float2(r[k].x, r[k].y);
+                    lds[row * RS + col + 1] = make_float2(r[k].z, r[k].w);
+                } else {
+                    lds[(i / ROW) * RS + (i % ROW)] = r[k];
+                }
+            }
+        }
+    }
+};
+
+template <int ROWS, int ROW, int RS, int T>
+__device__ __forceinline__ void lds_to_tile(const float2* lds, float2* g, int tid, int rows = ROWS)
+{
+    if constexpr (ROW % 2 == 0) {
+        constexpr int PAIRS = ROWS * ROW / 2, IT = (PAIRS + T - 1) / T;
+        float4* g4 = reinterpret_cast<float4*>(g);
+        float4 r[IT];
+        const int lim = rows * ROW / 2;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (i < lim) {
+                const int e = 2 * i, row = e / ROW, col = e % ROW;
+                const float2 a = lds[row * RS + col], b = lds[row * RS + col + 1];
+                r[k] = make_float4(a.x, a.y, b.x, b.y);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (i < lim) g4[i] = r[k];
+        }
+    } else {
+        constexpr int E = ROWS * ROW, IT = (E + T - 1) / T;
+        float2 r[IT];
+        const int lim = rows * ROW;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (i < lim) r[k] = lds[(i / ROW) * RS + (i % ROW)];
+        }
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (i < lim) g[i] = r[k];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ cube --
 
 template <int N>
@@ -81,14 +203,10 @@ k_cube(const float2* in, float2* out, const float2* __restrict__ tw)
 {
     using G = CubeGeom<N>;
     constexpr int T = G::T;
-    constexpr int V = N * N * N;
     __shared__ float2 lds[G::WORDS];
     const int tid = threadIdx.x;
-    const long base = (long)blockIdx.x * V;
-    for (int i = tid; i < V; i += T) {
-        const int x = i % N, y = (i / N) % N, z = i / (N * N);
-        lds[z * G::ZS + y * G::YS + x] = in[base + i];
-    }
+    const long base = (long)blockIdx.x * (N * N * N);
+    tile_to_lds<N * N, N, G::YS, T>(in + base, lds, tid);
     __syncthreads();
     // x: lines (z, y), contiguous elements
     fft_lds_all<N, S, N * N, T, G::YS, 1>(lds, tw, tid);
@@ -104,10 +222,7 @@ k_cube(const float2* in, float2* out, const float2* __restrict__ tw)
         run_tail<N, S, N * N, T, 0, true>(a, a, tw, tid);
         __syncthreads();
     }
-    for (int i = tid; i < V; i += T) {
-        const int x = i % N, y = (i / N) % N, z = i / (N * N);
-        out[base + i] = lds[z * G::ZS + y * G::YS + x];
-    }
+    lds_to_tile<N * N, N, G::YS, T>(lds, out + base, tid);
 }
 
 // ----------------------------------------------------------------- plane --
@@ -120,30 +235,214 @@ struct PlaneGeom {
 };
 
 // Global accessor for the y pass's final store: line = x, element = y.
-template <int N>
+// COH: device-coherent (write-through) stores.
+template <int N, bool COH = false>
 struct PlaneColOut {
     float2* p;
     __device__ __forceinline__ float2 load(int, int) const { return float2{}; }
-    __device__ __forceinline__ void store(int x, int y, float2 v) const { p[y * N + x] = v; }
+    __device__ __forceinline__ void store(int x, int y, float2 v) const
+    {
+        if constexpr (COH) store_coherent(p + y * N + x, v);
+        else p[y * N + x] = v;
+    }
 };
+
+// One xy-plane: `in` and `out` point at the plane's first element.
+// COH: the plane's output is stored device-coherently.
+template <int N, int S, int T, bool COH = false>
+__device__ __forceinline__ void plane_body(const float2* in, float2* out, const float2* __restrict__ tw,
+                                           float2* lds, int tid)
+{
+    constexpr int RS = PlaneGeom<N>::RS;
+    tile_to_lds<N, N, RS, T>(in, lds, tid);
+    __syncthreads();
+    // x transform: lines = y
+    fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
+    // y transform: lines = x; last stage straight to global
+    const LdsAcc<1, RS> col{lds};
+    const PlaneColOut<N, COH> dst{out};
+    run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
+}
 
 template <int N, int S>
 __global__ void __launch_bounds__(PlaneGeom<N>::T)
 k_plane(const float2* in, float2* out, const float2* __restrict__ tw)
 {
-    using G = PlaneGeom<N>;
-    constexpr int T = G::T;
-    __shared__ float2 lds[G::WORDS];
-    const int tid = threadIdx.x;
+    __shared__ float2 lds[PlaneGeom<N>::WORDS];
     const long base = (long)blockIdx.x * N * N;
-    for (int i = tid; i < N * N; i += T) lds[(i / N) * G::RS + (i % N)] = in[base + i];
-    __syncthreads();
-    // x transform: lines = y
-    fft_lds_all<N, S, N, T, G::RS, 1>(lds, tw, tid);
-    // y transform: lines = x; last stage straight to global
-    const LdsAcc<1, G::RS> col{lds};
-    const PlaneColOut<N> dst{out + base};
-    run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
+    plane_body<N, S, PlaneGeom<N>::T>(in + base, out + base, tw, lds, threadIdx.x);
+}
+
+// Persistent form of the plane pass: workgroup w transforms planes
+// w, w + G, w + 2G, ... and loads plane p + G into registers while plane p is
+// being transformed, so HBM latency overlaps the LDS/VALU phases.
+template <int N, int S>
+__global__ void __launch_bounds__(PlaneGeom<N>::T)
+k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long planes)
+{
+    constexpr int T = PlaneGeom<N>::T, RS = PlaneGeom<N>::RS;
+    __shared__ float2 lds[PlaneGeom<N>::WORDS];
+    const int tid = threadIdx.x;
+    TileRegs<N, N, T> regs;
+    long p = blockIdx.x;
+    if (p < planes) regs.load(in + p * N * N, tid);
+    for (; p < planes; p += gridDim.x) {
+        regs.template store_lds<RS>(lds, tid);
+        __syncthreads();
+        const long pn = p + gridDim.x;
+        if (pn < planes) regs.load(in + pn * N * N, tid);
+        fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
+        const LdsAcc<1, RS> col{lds};
+        const PlaneColOut<N> dst{out + p * N * N};
+        run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
+        __syncthreads();
+    }
+}
+
+// One xz-slab for fixed (b, y): N lines (all x) of N points along z, element
+// z of line x at base[z * es + x].  Loads and stores run with lanes along x.
+// COH: the slab's input is loaded device-coherently.
+template <int N, int S, int T, bool COH = false>
+__device__ __forceinline__ void slab_body(const float2* in, float2* out, long es, const float2* __restrict__ tw,
+                                          float2* lds, int tid)
+{
+    constexpr int LP = PlaneGeom<N>::RS;
+    using P = Plan1D<N>;
+    const GlobLines<COH> g{in, out, es};
+    if constexpr (P::stages == 1) {
+        fft_stage<N, 0, S, N, T, true, false>(g, g, tw, tid);
+    } else {
+        const LdsAcc<1, LP> a{lds};
+        fft_stage<N, 0, S, N, T, true, false>(g, a, tw, tid);
+        __syncthreads();
+        run_tail<N, S, N, T, 1, false>(a, g, tw, tid);
+    }
+}
+
+// ------------------------------------------------------------ fused pass --
+
+// Control block of the persistent kernel (device memory owned by the plan,
+// zero between executions: the last workgroup to leave resets it).
+struct FusedCtl {
+    unsigned head;     // next work item
+    unsigned exited;   // workgroups that have left the item loop
+    unsigned timeouts; // bounded waits that expired (0 in correct operation)
+    unsigned pad;
+    unsigned done[1];  // per grid: plane items completed (batch entries)
+};
+
+// Work item order for `batch` grids with dependency lag `lag` (in grids):
+// phase p emits the N plane items of grid p (p < batch) followed by the N
+// slab items of grid p - lag (p >= lag).  Every plane item of grid g is
+// dequeued before any slab item of g, so a slab item only ever waits for
+// items already held by running workgroups.
+struct Item {
+    int slab;
+    int g;
+    int idx;
+};
+
+__device__ __forceinline__ Item decode_item(long i, int N, int batch, int lag)
+{
+    const int n1 = lag < batch ? lag : batch;
+    const long s1 = (long)n1 * N;
+    if (i < s1) return {0, (int)(i / N), (int)(i % N)};
+    i -= s1;
+    const int n2 = batch > lag ? batch - lag : 0;
+    const long s2 = (long)n2 * 2 * N;
+    if (i < s2) {
+        const int ph = (int)(i / (2 * N)), r = (int)(i % (2 * N)), p = lag + ph;
+        return r < N ? Item{0, p, r} : Item{1, p - lag, r - N};
+    }
+    i -= s2;
+    return {1, n2 + (int)(i / N), (int)(i % N)};
+}
+
+constexpr unsigned kSpinLimit = 1u << 22;
+
+// Hand-off protocol between workgroups (one launch, no cache-wide
+// write-back or invalidate): plane items store their output with
+// device-coherent write-through stores; a plane item is published (its
+// grid's counter incremented) only after every wave of the workgroup has
+// waited for all its outstanding memory operations, which includes those
+// stores; slab items read the intermediate with device-coherent loads issued
+// after they have observed the counter.  Publishing is deferred to the next
+// item's load phase so that the store latency overlaps useful work.
+template <int N, int S>
+__global__ void __launch_bounds__(PlaneGeom<N>::T)
+k_fused(const float2* in, float2* out, const float2* __restrict__ tw, FusedCtl* ctl, int batch, int lag,
+        int chunk)
+{
+    constexpr int T = PlaneGeom<N>::T;
+    constexpr long V = (long)N * N * N;
+    __shared__ float2 lds[PlaneGeom<N>::WORDS];
+    __shared__ int item_sh;
+    const int tid = threadIdx.x;
+    const long total = 2L * batch * N;
+    int pending = -1;
+    long next = -1, chunk_end = -1;   // items of the current chunk (dynamic) or stride (static)   // grid of this workgroup's last unpublished plane item (uniform)
+    auto publish = [&]() {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (pending >= 0 && tid == 0)
+            __hip_atomic_fetch_add(&ctl->done[pending], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pending = -1;
+    };
+    for (;;) {
+        long it;
+        if (chunk <= 0) {                    // static round robin
+            it = next < 0 ? (long)blockIdx.x : next + gridDim.x;
+            next = it;
+        } else {
+            if (next < 0 || next + 1 >= chunk_end) {
+                if (tid == 0) item_sh = (int)atomicAdd(&ctl->head, (unsigned)chunk);
+                __syncthreads();
+                next = item_sh;
+                chunk_end = next + chunk;
+            } else {
+                ++next;
+            }
+            it = next;
+        }
+        if (it >= total) break;
+        const Item w = decode_item(it, N, batch, lag);
+        if (!w.slab) {
+            const long base = w.g * V + (long)w.idx * N * N;
+            constexpr int RS = PlaneGeom<N>::RS;
+            tile_to_lds<N, N, RS, T>(in + base, lds, tid);
+            publish();   // previous plane's stores are complete by now
+            fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
+            const LdsAcc<1, RS> col{lds};
+            const PlaneColOut<N, true> dst{out + base};
+            run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
+            pending = w.g;
+        } else {
+            publish();
+            if (tid == 0) {
+                unsigned n = 0;
+                while (__hip_atomic_load(&ctl->done[w.g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)N) {
+                    if (++n >= kSpinLimit) {
+                        atomicAdd(&ctl->timeouts, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            __syncthreads();
+            const long base = w.g * V + (long)w.idx * N;
+            slab_body<N, S, T, true>(out + base, out + base, (long)N * N, tw, lds, tid);
+        }
+        __syncthreads();   // LDS and item_sh reuse
+    }
+    publish();
+    if (tid == 0) {
+        const unsigned prev = __hip_atomic_fetch_add(&ctl->exited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gridDim.x - 1) {
+            for (int g = 0; g < batch; ++g) ctl->done[g] = 0;
+            ctl->head = 0;
+            __hip_atomic_store(&ctl->exited, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // ---------------------------------------------------------- strided axis --

@@ -7,12 +7,17 @@
 namespace fft3d {
 
 struct AxisMap;
+struct FusedCtl;
 
 using CubeFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long grids, hipStream_t st);
 using PlaneFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, hipStream_t st);
+using PlanePfFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, int grid,
+                                 hipStream_t st);
 using AxisStrFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, const AxisMap& m,
                                  hipStream_t st);
 using AxisRowFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long rows, hipStream_t st);
+using FusedFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, FusedCtl* ctl, int batch, int lag,
+                               int grid, int chunk, hipStream_t st);
 
 // Largest cubic length handled by the whole-grid-in-LDS kernel.
 constexpr int kCubeMaxN = 16;
@@ -22,8 +27,13 @@ constexpr int kRowLines = 16;
 
 CubeFn cube_fn(int n, int sign);
 PlaneFn plane_fn(int n, int sign);
+PlanePfFn plane_pf_fn(int n, int sign);
+int plane_pf_blocks_per_cu(int n);
 AxisStrFn axis_str_fn(int n, int sign);
 AxisRowFn axis_row_fn(int n, int sign);
+FusedFn fused_fn(int n, int sign);
+// Workgroups of the fused kernel that fit on one compute unit at once.
+int fused_blocks_per_cu(int n);
 
 // Kernel geometry (threads, LDS bytes) for diagnostics.
 struct KernelInfo {
@@ -34,5 +44,6 @@ KernelInfo cube_info(int n);
 KernelInfo plane_info(int n);
 KernelInfo axis_str_info(int n);
 KernelInfo axis_row_info(int n);
+KernelInfo fused_info(int n);
 
 }  // namespace fft3d

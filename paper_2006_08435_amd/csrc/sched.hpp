@@ -89,6 +89,13 @@ __host__ __device__ constexpr bool size_supported(int n)
 
 }  // namespace fft3d
 
+// X-macro over the cubic lengths served by the persistent fused kernel
+// (smaller cubes use the whole-grid-in-LDS kernel).
+#define FFT3D_FOR_EACH_FUSED_SIZE(X)                                           \
+    X(18) X(20) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(45) X(48) X(50)    \
+    X(54) X(60) X(64) X(72) X(75) X(80) X(81) X(90) X(96) X(100) X(108)        \
+    X(120) X(125) X(128)
+
 // X-macro over every supported length.
 #define FFT3D_FOR_EACH_SIZE(X)                                                 \
     X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(18)      \

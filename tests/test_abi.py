@@ -63,11 +63,11 @@ def test_null_handles():
 def test_strerror_covers_codes():
     lib = _lib().lib()
     seen = set()
-    for c in range(0, -8, -1):
+    for c in range(0, -9, -1):
         s = lib.fft3d_strerror(c).decode()
         assert s and s != "unknown status"
         seen.add(s)
-    assert len(seen) == 8
+    assert len(seen) == 9
     assert lib.fft3d_strerror(-99).decode() == "unknown status"
 
 
