@@ -129,6 +129,35 @@ int fft3d_plan_passes(fft3d_plan_t plan);
 int fft3d_plan_check(fft3d_plan_t plan);
 int fft3d_exec_pass(fft3d_plan_t plan, int pass, const void *in, void *out, fft3d_stream_t stream);
 
+/*
+ * Plane-wave local-potential energy and its gradient (the operator
+ * evaluation through 3D FFTs that Section I places on the critical path of
+ * plane-wave DFT; the FP32-vs-FP64 energy comparison of Section III is its
+ * accuracy question).  For a plan of `batch` orbitals c_n (FP32, nx == ny,
+ * either direction):
+ *
+ *   fft3d_energy_fwd:  psi_n = unnormalised inverse transform of c_n (sign
+ *     +1), written to `psi` (device, same size as c; psi == c allowed), and
+ *     E = sum_n sum_r V(r) |psi_n(r)|^2 written to E_dev[0] (device double).
+ *     V is a device float array [nz][ny][nx] shared by all orbitals.  The
+ *     products are FP32, the sum is FP64 in a fixed order (deterministic).
+ *   fft3d_energy_bwd:  grad_c = forward transform (sign -1) of
+ *     2 * gE_dev[0] * V * psi_n -- the gradient of gE * E in the convention
+ *     dE/dRe(c) + i dE/dIm(c) (the adjoint of the unnormalised inverse is the
+ *     unnormalised forward transform).  If have_psi != 0, c_or_psi holds psi
+ *     (e.g. from fft3d_energy_fwd); otherwise it holds c and psi is
+ *     recomputed into grad_c first.  grad_c may equal c_or_psi.
+ *
+ * Both enqueue on `stream` without host synchronisation.  Returns FFT3D_OK,
+ * FFT3D_E_INVALID_ARG (NULL pointer), FFT3D_E_ALIGNMENT (data not 16-byte,
+ * doubles not 8-byte aligned), FFT3D_E_UNSUPPORTED (plan not FP32 or
+ * nx != ny) or FFT3D_E_LAUNCH.
+ */
+int fft3d_energy_fwd(fft3d_plan_t plan, const void *c, const float *V, void *psi, double *E_dev,
+                     fft3d_stream_t stream);
+int fft3d_energy_bwd(fft3d_plan_t plan, const void *c_or_psi, int have_psi, const float *V, const double *gE_dev,
+                     void *grad_c, fft3d_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

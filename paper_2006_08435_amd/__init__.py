@@ -133,5 +133,13 @@ def ifftn(x, out=None):
     return _transform(x, FFT3D_INVERSE, out)
 
 
+def __getattr__(name):
+    # autograd wrappers are imported lazily (they need torch at import time)
+    if name in ("FFT3D", "IFFT3D", "LocalPotentialEnergy", "local_potential_energy", "energy_and_psi"):
+        from . import autograd
+        return getattr(autograd, name)
+    raise AttributeError(name)
+
+
 __all__ = ["Plan", "get_plan", "fftn", "ifftn", "Fft3dError", "FFT3D_FORWARD",
            "FFT3D_INVERSE", "FFT3D_FP32", "FFT3D_FP16_SCALED", "FFT3D_BF16_SCALED"]

@@ -87,7 +87,11 @@ struct fft3d_plan_s {
     int device;
     float2* d_tw;           // all tables of the plan, one allocation
     long tw_x, tw_y, tw_z;  // offsets (elements) of each dimension's table
+    long tw_rx, tw_ry, tw_rz;  // the same tables for the opposite sign
     long vol;
+    double* partials;       // energy: one FP64 partial per z-pass workgroup (nx == ny plans)
+    long n_partials;
+    int pf_grid;            // workgroups of the persistent plane pass (nx == ny plans)
     std::vector<Pass> passes;
     FusedCtl* ctl;   // persistent-kernel control block (kFused)
     int fused_grid;  // workgroups of the persistent launch
@@ -155,17 +159,20 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
     // One table per dimension (identical lengths share nothing on purpose:
     // the tables are tiny and separate offsets keep the exec path simple).
     std::vector<float2> tab;
-    auto append = [&](int n) {
+    auto append = [&](int n, int sign) {
         const long off = (long)tab.size();
-        std::vector<float2> t = twiddles(n, direction);
+        std::vector<float2> t = twiddles(n, sign);
         tab.insert(tab.end(), t.begin(), t.end());
         // keep every table 16-byte aligned
         if (tab.size() % 2) tab.push_back(make_float2(0.f, 0.f));
         return off;
     };
-    p->tw_x = append(nx);
-    p->tw_y = append(ny);
-    p->tw_z = append(nz);
+    p->tw_x = append(nx, direction);
+    p->tw_y = append(ny, direction);
+    p->tw_z = append(nz, direction);
+    p->tw_rx = append(nx, -direction);
+    p->tw_ry = append(ny, -direction);
+    p->tw_rz = append(nz, -direction);
     if (tab.empty()) tab.push_back(make_float2(0.f, 0.f));
     const size_t bytes = tab.size() * sizeof(float2);
     if (test_fail_alloc() || hipMalloc((void**)&p->d_tw, bytes) != hipSuccess) {
@@ -180,6 +187,21 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
         delete p;
         set_error(FFT3D_E_LAUNCH);
         return nullptr;
+    }
+    if (nx == ny) {
+        // energy path: persistent plane pass + strided z pass with fused epilogue
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+        const long resident = (long)plane_pf_blocks_per_cu(nx) * cus, planes = (long)batch * nz;
+        p->pf_grid = (int)(planes < resident ? planes : resident);
+        p->n_partials = axis_str_blocks((long)batch * ny * nx);
+        if (hipMalloc((void**)&p->partials, sizeof(double) * p->n_partials) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(p->d_tw);
+            delete p;
+            set_error(FFT3D_E_ALLOC);
+            return nullptr;
+        }
     }
     const long B = batch;
     const AxisMap zmap{B * ny * nx, nx, ny, vol, (long)nx, (long)nx * ny};
@@ -212,7 +234,7 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
                 cus = 1;
             const long resident = (long)plane_pf_blocks_per_cu(nx) * cus;
             const long planes = B * nz;
-            p->passes.push_back({Pass::kPlanePfK, nx, planes, {}, p->tw_x, (int)(planes < resident ? planes : resident)});
+            p->passes.push_back({Pass::kPlanePfK, nx, planes, {}, p->tw_x, p->pf_grid});
         } else {
             p->passes.push_back({Pass::kPlaneK, nx, B * nz, {}, p->tw_x});
         }
@@ -230,6 +252,7 @@ int fft3d_destroy(fft3d_plan_t p)
     if (!p) return FFT3D_OK;
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->ctl) (void)hipFree(p->ctl);
+    if (p->partials) (void)hipFree(p->partials);
     delete p;
     return FFT3D_OK;
 }
@@ -248,9 +271,10 @@ static hipError_t run_pass(const fft3d_plan_s* p, const Pass& ps, const float2* 
     switch (ps.kind) {
     case Pass::kCubeK: return cube_fn(ps.n, S)(src, dst, tw, ps.count, st);
     case Pass::kPlaneK: return plane_fn(ps.n, S)(src, dst, tw, ps.count, st);
-    case Pass::kPlanePfK: return plane_pf_fn(ps.n, S)(src, dst, tw, ps.count, ps.grid, st);
+    case Pass::kPlanePfK:
+        return plane_pf_fn(ps.n, S)(src, dst, tw, ps.count, ps.grid, 0, nullptr, nullptr, 1, st);
     case Pass::kRowK: return axis_row_fn(ps.n, S)(src, dst, tw, ps.count, st);
-    case Pass::kStrK: return axis_str_fn(ps.n, S)(src, dst, tw, ps.map, st);
+    case Pass::kStrK: return axis_str_fn(ps.n, S)(src, dst, tw, ps.map, 0, nullptr, nullptr, 0, st);
     case Pass::kFusedK:
         return fused_fn(ps.n, S)(src, dst, tw, p->ctl, p->batch, p->fused_lag, p->fused_grid, p->fused_chunk, st);
     }
@@ -296,6 +320,68 @@ int fft3d_exec_pass(fft3d_plan_t p, int pass, const void* in, void* out, fft3d_s
     if (pass < 0 || pass >= (int)p->passes.size()) return FFT3D_E_INVALID_ARG;
     const hipError_t e = run_pass(p, p->passes[pass], static_cast<const float2*>(in), static_cast<float2*>(out),
                                   reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
+// Two-pass transform of sign `sign` (plane pass, then z pass) with the
+// optional gradient prologue (V, gE) and energy epilogue (V, E partials).
+static hipError_t energy_transform(const fft3d_plan_s* p, int sign, const float2* src, float2* dst,
+                                   const float* V, const double* gE, bool epilogue, hipStream_t st)
+{
+    const int n = p->nx, nz = p->nz;
+    const bool same = sign == p->direction;
+    const float2* twx = p->d_tw + (same ? p->tw_x : p->tw_rx);
+    const float2* twz = p->d_tw + (same ? p->tw_z : p->tw_rz);
+    const long planes = (long)p->batch * nz;
+    hipError_t e = plane_pf_fn(n, sign)(src, dst, twx, planes, p->pf_grid, gE != nullptr, V, gE, nz, st);
+    if (e != hipSuccess) return e;
+    const AxisMap zmap{(long)p->batch * p->ny * n, n, p->ny, p->vol, (long)n, (long)n * p->ny};
+    if (nz > 1 || epilogue) e = axis_str_fn(nz, sign)(dst, dst, twz, zmap, epilogue, V, p->partials, p->vol, st);
+    return e;
+}
+
+static int energy_args(fft3d_plan_t p, const void* a, const void* b, const void* V, const void* d)
+{
+    if (!p || !a || !b || !V || !d) return FFT3D_E_INVALID_ARG;
+    if (((uintptr_t)a % 16) || ((uintptr_t)b % 16) || ((uintptr_t)V % 16) || ((uintptr_t)d % 8))
+        return FFT3D_E_ALIGNMENT;
+    if (p->precision != FFT3D_FP32 || p->nx != p->ny || !p->partials) return FFT3D_E_UNSUPPORTED;
+    return FFT3D_OK;
+}
+
+int fft3d_energy_fwd(fft3d_plan_t p, const void* c, const float* V, void* psi, double* E_dev, fft3d_stream_t stream)
+{
+    const int rc = energy_args(p, c, psi, V, E_dev);
+    if (rc != FFT3D_OK) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = energy_transform(p, FFT3D_INVERSE, static_cast<const float2*>(c), static_cast<float2*>(psi), V,
+                                    nullptr, true, st);
+    if (e == hipSuccess) e = launch_sum_partials(p->partials, p->n_partials, E_dev, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
+int fft3d_energy_bwd(fft3d_plan_t p, const void* c_or_psi, int have_psi, const float* V, const double* gE_dev,
+                     void* grad_c, fft3d_stream_t stream)
+{
+    const int rc = energy_args(p, c_or_psi, grad_c, V, gE_dev);
+    if (rc != FFT3D_OK) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const float2* src = static_cast<const float2*>(c_or_psi);
+    float2* g = static_cast<float2*>(grad_c);
+    hipError_t e = hipSuccess;
+    if (!have_psi) {   // recompute psi = IFFT(c) into the gradient buffer
+        e = energy_transform(p, FFT3D_INVERSE, src, g, nullptr, nullptr, false, st);
+        src = g;
+    }
+    if (e == hipSuccess) e = energy_transform(p, FFT3D_FORWARD, src, g, V, gE_dev, false, st);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return FFT3D_E_LAUNCH;

@@ -4,13 +4,41 @@
 
 namespace fft3d {
 
-template <int N, int S>
-static hipError_t launch_axis_str(const float2* in, float2* out, const float2* tw, const AxisMap& m,
-                                  hipStream_t st)
+// Sum of n FP64 partials in a fixed order (one workgroup of 256 threads).
+__global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__ p, long n, double* __restrict__ out)
 {
-    const long blocks = (m.lines + kAxisLines - 1) / kAxisLines;
-    hipLaunchKernelGGL((k_axis_str<N, S, kAxisLines>), dim3((unsigned)blocks), dim3(AxisGeom<N, kAxisLines>::T), 0,
-                       st, in, out, tw, m);
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (long i = tid; i < n; i += 256) s += p[i];
+    red[tid] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) out[0] = red[0];
+}
+
+long axis_str_blocks(long lines) { return (lines + kAxisLines - 1) / kAxisLines; }
+
+hipError_t launch_sum_partials(const double* partials, long n, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partials, n, out);
+    return hipGetLastError();
+}
+
+template <int N, int S>
+static hipError_t launch_axis_str(const float2* in, float2* out, const float2* tw, const AxisMap& m, int energy,
+                                  const float* V, double* partials, long vol, hipStream_t st)
+{
+    const long blocks = axis_str_blocks(m.lines);
+    if (energy)
+        hipLaunchKernelGGL((k_axis_str<N, S, kAxisLines, true>), dim3((unsigned)blocks),
+                           dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, out, tw, m, V, partials, vol);
+    else
+        hipLaunchKernelGGL((k_axis_str<N, S, kAxisLines, false>), dim3((unsigned)blocks),
+                           dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, out, tw, m, V, partials, vol);
     return hipGetLastError();
 }
 

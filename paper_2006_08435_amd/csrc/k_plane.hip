@@ -12,10 +12,15 @@ static hipError_t launch_plane(const float2* in, float2* out, const float2* tw, 
 }
 
 template <int N, int S>
-static hipError_t launch_plane_pf(const float2* in, float2* out, const float2* tw, long planes, int grid,
-                                  hipStream_t st)
+static hipError_t launch_plane_pf(const float2* in, float2* out, const float2* tw, long planes, int grid, int scale,
+                                  const float* V, const double* gE, int nz, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_plane_pf<N, S>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out, tw, planes);
+    if (scale)
+        hipLaunchKernelGGL((k_plane_pf<N, S, true>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out, tw,
+                           planes, V, gE, nz);
+    else
+        hipLaunchKernelGGL((k_plane_pf<N, S, false>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out, tw,
+                           planes, V, gE, nz);
     return hipGetLastError();
 }
 
@@ -23,7 +28,7 @@ template <int N>
 static int plane_pf_occ()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_plane_pf<N, -1>),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_plane_pf<N, -1, false>),
                                                      PlaneGeom<N>::T, 0) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
@@ -41,7 +46,7 @@ static int plane_pf_occ()
 PlanePfFn plane_pf_fn(int n, int sign)
 {
     switch (n) {
-        FFT3D_FOR_EACH_FUSED_SIZE(FFT3D_PLANE_PF_CASE)
+        FFT3D_FOR_EACH_SIZE(FFT3D_PLANE_PF_CASE)
     default: return nullptr;
     }
 }
@@ -49,7 +54,7 @@ PlanePfFn plane_pf_fn(int n, int sign)
 int plane_pf_blocks_per_cu(int n)
 {
     switch (n) {
-        FFT3D_FOR_EACH_FUSED_SIZE(FFT3D_PLANE_PF_OCC)
+        FFT3D_FOR_EACH_SIZE(FFT3D_PLANE_PF_OCC)
     default: return 1;
     }
 }

@@ -129,6 +129,39 @@ struct TileRegs {
             if (UNITS % T == 0 || i < UNITS) r[k] = gu[i];
         }
     }
+    // Load the real factors f[e] matching this tile's elements (same unit
+    // pattern: pairs of floats for even rows, single floats otherwise).
+    template <class FR>
+    __device__ __forceinline__ void load_factors(FR& fr, const float* f, int tid) const
+    {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (UNITS % T == 0 || i < UNITS) {
+                if constexpr (PAIRS) fr.r[k] = reinterpret_cast<const float2*>(f)[i];
+                else fr.r[k] = f[i];
+            }
+        }
+    }
+    template <int RS, class FR>
+    __device__ __forceinline__ void store_lds_scaled(float2* lds, int tid, const FR& fr, float s) const
+    {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (UNITS % T == 0 || i < UNITS) {
+                if constexpr (PAIRS) {
+                    const int e = 2 * i, row = e / ROW, col = e % ROW;
+                    const float a = s * fr.r[k].x, b = s * fr.r[k].y;
+                    lds[row * RS + col] = make_float2(a * r[k].x, a * r[k].y);
+                    lds[row * RS + col + 1] = make_float2(b * r[k].z, b * r[k].w);
+                } else {
+                    const float a = s * fr.r[k];
+                    lds[(i / ROW) * RS + (i % ROW)] = make_float2(a * r[k].x, a * r[k].y);
+                }
+            }
+        }
+    }
     template <int RS>
     __device__ __forceinline__ void store_lds(float2* lds, int tid) const
     {
@@ -146,6 +179,14 @@ struct TileRegs {
             }
         }
     }
+};
+
+// Register copy of the real factors of one tile (see TileRegs::load_factors).
+template <int ROWS, int ROW, int T>
+struct FactorRegs {
+    using TR = TileRegs<ROWS, ROW, T>;
+    using U = typename std::conditional<TR::PAIRS, float2, float>::type;
+    U r[TR::IT];
 };
 
 template <int ROWS, int ROW, int RS, int T>
@@ -276,21 +317,36 @@ k_plane(const float2* in, float2* out, const float2* __restrict__ tw)
 // Persistent form of the plane pass: workgroup w transforms planes
 // w, w + G, w + 2G, ... and loads plane p + G into registers while plane p is
 // being transformed, so HBM latency overlaps the LDS/VALU phases.
-template <int N, int S>
+//
+// SCALE: every input value at grid position r is first multiplied by the real
+// factor 2 * gE[0] * V[r] (V: one [nz][N][N] grid shared by the batch) -- the
+// prologue of the energy gradient.
+template <int N, int S, bool SCALE = false>
 __global__ void __launch_bounds__(PlaneGeom<N>::T)
-k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long planes)
+k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long planes, const float* __restrict__ V,
+           const double* __restrict__ gE, int nz)
 {
     constexpr int T = PlaneGeom<N>::T, RS = PlaneGeom<N>::RS;
     __shared__ float2 lds[PlaneGeom<N>::WORDS];
     const int tid = threadIdx.x;
     TileRegs<N, N, T> regs;
+    FactorRegs<N, N, T> vr;
+    float scale = 0.f;
+    if constexpr (SCALE) scale = (float)(2.0 * gE[0]);
     long p = blockIdx.x;
-    if (p < planes) regs.load(in + p * N * N, tid);
+    if (p < planes) {
+        regs.load(in + p * N * N, tid);
+        if constexpr (SCALE) regs.load_factors(vr, V + (p % nz) * N * N, tid);
+    }
     for (; p < planes; p += gridDim.x) {
-        regs.template store_lds<RS>(lds, tid);
+        if constexpr (SCALE) regs.template store_lds_scaled<RS>(lds, tid, vr, scale);
+        else regs.template store_lds<RS>(lds, tid);
         __syncthreads();
         const long pn = p + gridDim.x;
-        if (pn < planes) regs.load(in + pn * N * N, tid);
+        if (pn < planes) {
+            regs.load(in + pn * N * N, tid);
+            if constexpr (SCALE) regs.load_factors(vr, V + (pn % nz) * N * N, tid);
+        }
         fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
         const LdsAcc<1, RS> col{lds};
         const PlaneColOut<N> dst{out + p * N * N};
@@ -465,9 +521,43 @@ struct AxisGeom {
     static_assert(T % L == 0 || L % T == 0, "tile lines and threads must nest");
 };
 
-template <int N, int S, int L>
+// Final-store accessor of the energy epilogue: stores psi and accumulates
+// V[r] |psi(r)|^2 (FP32 product, FP64 running sum) for this thread's points.
+struct EnergyStore {
+    const float2* src;
+    float2* dst;
+    long es;
+    const float* v;
+    mutable double acc;
+    __device__ __forceinline__ float2 load(int, int e) const { return src[(long)e * es]; }
+    __device__ __forceinline__ void store(int, int e, float2 val) const
+    {
+        dst[(long)e * es] = val;
+        acc += (double)(v[(long)e * es] * fmaf(val.x, val.x, val.y * val.y));
+    }
+};
+
+// Fixed-order workgroup sum of one double per thread; result valid in thread 0.
+template <int T>
+__device__ __forceinline__ double block_sum(double x, double* red, int tid)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = x;
+    __syncthreads();
+    double t = 0.0;
+    if (tid == 0)
+        for (int w = 0; w < T / 64; ++w) t += red[w];
+    return t;
+}
+
+// ENERGY: the pass is the last one of an inverse transform psi = IFFT(c);
+// while storing psi it accumulates sum V |psi|^2 and writes one FP64 partial
+// per workgroup to partials[blockIdx.x] (V indexed by position in the grid).
+template <int N, int S, int L, bool ENERGY = false>
 __global__ void __launch_bounds__((AxisGeom<N, L>::T))
-k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap m)
+k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap m, const float* __restrict__ V,
+           double* __restrict__ partials, long vol)
 {
     using G = AxisGeom<N, L>;
     using P = Plan1D<N>;
@@ -486,15 +576,31 @@ k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap
         gbase = (o / m.odiv) * m.shi + (o % m.odiv) * m.slo + x;
     }
     const GlobStrided g{in + gbase, out + gbase, m.es};
-    if constexpr (P::stages == 1) {
-        fft_stage<N, 0, S, L, T, true, false>(g, g, tw, tid, valid);
+    if constexpr (ENERGY) {
+        __shared__ double red[T / 64];
+        const EnergyStore eg{in + gbase, out + gbase, m.es, V + (gbase % vol), 0.0};
+        if constexpr (P::stages == 1) {
+            fft_stage<N, 0, S, L, T, true, false>(g, eg, tw, tid, valid);
+        } else {
+            const LdsAcc<1, G::LP> a{lds};
+            fft_stage<N, 0, S, L, T, true, false>(g, a, tw, tid, valid);
+            __syncthreads();
+            run_tail<N, S, L, T, 1, false>(a, eg, tw, tid, valid);
+        }
+        const double t = block_sum<T>(eg.acc, red, tid);
+        if (tid == 0) partials[blockIdx.x] = t;
     } else {
-        const LdsAcc<1, G::LP> a{lds};
-        fft_stage<N, 0, S, L, T, true, false>(g, a, tw, tid, valid);
-        __syncthreads();
-        run_tail<N, S, L, T, 1, false>(a, g, tw, tid, valid);
+        if constexpr (P::stages == 1) {
+            fft_stage<N, 0, S, L, T, true, false>(g, g, tw, tid, valid);
+        } else {
+            const LdsAcc<1, G::LP> a{lds};
+            fft_stage<N, 0, S, L, T, true, false>(g, a, tw, tid, valid);
+            __syncthreads();
+            run_tail<N, S, L, T, 1, false>(a, g, tw, tid, valid);
+        }
     }
 }
+
 
 // --------------------------------------------------------------- x rows --
 

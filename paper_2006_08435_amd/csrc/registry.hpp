@@ -11,10 +11,13 @@ struct FusedCtl;
 
 using CubeFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long grids, hipStream_t st);
 using PlaneFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, hipStream_t st);
-using PlanePfFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, int grid,
-                                 hipStream_t st);
-using AxisStrFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, const AxisMap& m,
-                                 hipStream_t st);
+// scale != 0: fused prologue, input at r multiplied by 2 gE[0] V[r].
+using PlanePfFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, int grid, int scale,
+                                 const float* V, const double* gE, int nz, hipStream_t st);
+// energy != 0: fused epilogue, V[r]|out(r)|^2 summed into one FP64 partial
+// per workgroup (axis_str_blocks(m) of them) at `partials`.
+using AxisStrFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, const AxisMap& m, int energy,
+                                 const float* V, double* partials, long vol, hipStream_t st);
 using AxisRowFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long rows, hipStream_t st);
 using FusedFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, FusedCtl* ctl, int batch, int lag,
                                int grid, int chunk, hipStream_t st);
@@ -26,6 +29,8 @@ constexpr int kAxisLines = 64;
 constexpr int kRowLines = 16;
 
 CubeFn cube_fn(int n, int sign);
+long axis_str_blocks(long lines);
+hipError_t launch_sum_partials(const double* partials, long n, double* out, hipStream_t st);
 PlaneFn plane_fn(int n, int sign);
 PlanePfFn plane_pf_fn(int n, int sign);
 int plane_pf_blocks_per_cu(int n);
