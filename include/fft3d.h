@@ -130,6 +130,34 @@ int fft3d_plan_check(fft3d_plan_t plan);
 int fft3d_exec_pass(fft3d_plan_t plan, int pass, const void *in, void *out, fft3d_stream_t stream);
 
 /*
+ * Heterogeneous batches in one launch.  `count` groups (1 <= count <= 16);
+ * group g holds batch[g] cubic grids of nx[g] = ny[g] = nz[g] points per
+ * side (sizes 24, 30, 32, 36, 40, 48, 50, 60, 64, 72, 80, 90, 96, 100, 120,
+ * 128; FP32).  fft3d_exec_many transforms every grid of every group with ONE
+ * persistent kernel launch: workgroups claim work items (xy-planes, then
+ * xz-slabs of each grid) from a queue, and a grid's z work waits on a
+ * per-grid counter of its finished planes.  `in` and `out` are HOST arrays of
+ * `count` device pointers, group g's buffer holding batch[g] grids in the
+ * layout of fft3d_exec (in[g] == out[g] allowed).  The launch is
+ * graph-capturable; a plan must not run concurrently with itself or with
+ * another persistent launch on a different stream.
+ *
+ * Returns NULL / FFT3D_E_UNSUPPORTED for non-cubic or unlisted sizes and
+ * other precisions.  The schedule (threads per workgroup, items per queue
+ * claim) is taken from the tuning cache ($FFT3D_TUNE_CACHE, default
+ * ~/.cache/fft3d/tune.json), else tuned at plan time when FFT3D_TUNE=1,
+ * else a default.
+ */
+fft3d_plan_t fft3d_plan_many(int count, const int *nx, const int *ny, const int *nz, const int *batch,
+                             int precision, int direction);
+int fft3d_exec_many(fft3d_plan_t plan, const void *const *in, void *const *out, fft3d_stream_t stream);
+/* Force a schedule of a many-plan: threads 512 or 1024, chunk 1..64 items per claim. */
+int fft3d_plan_set_schedule(fft3d_plan_t plan, int threads, int chunk);
+/* Time every schedule candidate on scratch buffers (synchronous), keep the
+ * fastest and record it in the tuning cache. */
+int fft3d_plan_tune(fft3d_plan_t plan);
+
+/*
  * Plane-wave local-potential energy and its gradient (the operator
  * evaluation through 3D FFTs that Section I places on the critical path of
  * plane-wave DFT; the FP32-vs-FP64 energy comparison of Section III is its

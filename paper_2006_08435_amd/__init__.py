@@ -88,6 +88,74 @@ class Plan:
             pass
 
 
+class PlanMany:
+    """Heterogeneous batch: groups of cubic grids transformed by one
+    persistent launch.  ``groups`` is a list of (n, batch) pairs."""
+
+    def __init__(self, groups, direction: int = FFT3D_FORWARD, precision="fp32"):
+        import ctypes
+        lib = _lib.lib()
+        k = len(groups)
+        arr = lambda vals: (ctypes.c_int * k)(*[int(v) for v in vals])
+        ns = arr([g[0] for g in groups])
+        bs = arr([g[1] for g in groups])
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = lib.fft3d_plan_many(k, ctypes.cast(ns, ctypes.c_void_p), ctypes.cast(ns, ctypes.c_void_p),
+                                ctypes.cast(ns, ctypes.c_void_p), ctypes.cast(bs, ctypes.c_void_p), prec,
+                                int(direction))
+        if not h:
+            raise Fft3dError(lib.fft3d_last_error(), "fft3d_plan_many(%r)" % (groups,))
+        self._h = h
+        self.groups = [(int(n), int(b)) for n, b in groups]
+        self.direction = int(direction)
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    def describe(self) -> str:
+        import ctypes
+        buf = ctypes.create_string_buffer(512)
+        _lib.lib().fft3d_plan_describe(self._h, buf, 512)
+        return buf.value.decode()
+
+    def set_schedule(self, threads: int, chunk: int) -> None:
+        _lib.check(_lib.lib().fft3d_plan_set_schedule(self._h, int(threads), int(chunk)), "set_schedule")
+
+    def tune(self) -> None:
+        _lib.check(_lib.lib().fft3d_plan_tune(self._h), "fft3d_plan_tune")
+
+    def exec_ptrs(self, in_ptrs, out_ptrs, stream_handle: int) -> None:
+        import ctypes
+        k = len(self.groups)
+        ia = (ctypes.c_void_p * k)(*in_ptrs)
+        oa = (ctypes.c_void_p * k)(*out_ptrs)
+        _lib.check(_lib.lib().fft3d_exec_many(self._h, ctypes.cast(ia, ctypes.c_void_p),
+                                              ctypes.cast(oa, ctypes.c_void_p), stream_handle), "fft3d_exec_many")
+
+    def exec(self, ins, outs=None, stream=None):
+        torch = _torch()
+        if outs is None:
+            outs = [torch.empty_like(t) for t in ins]
+        for (n, b), i, o in zip(self.groups, ins, outs):
+            for t in (i, o):
+                if not t.is_cuda or not t.is_contiguous() or t.numel() != b * n ** 3 or t.dtype != torch.complex64:
+                    raise ValueError("group tensors must be contiguous complex64 [%d, %d, %d, %d]" % (b, n, n, n))
+        self.exec_ptrs([t.data_ptr() for t in ins], [t.data_ptr() for t in outs], _stream_handle(stream))
+        return outs
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.lib().fft3d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 _cache = {}
 _cache_lock = threading.Lock()
 
@@ -141,5 +209,5 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-__all__ = ["Plan", "get_plan", "fftn", "ifftn", "Fft3dError", "FFT3D_FORWARD",
+__all__ = ["Plan", "PlanMany", "get_plan", "fftn", "ifftn", "Fft3dError", "FFT3D_FORWARD",
            "FFT3D_INVERSE", "FFT3D_FP32", "FFT3D_FP16_SCALED", "FFT3D_BF16_SCALED"]

@@ -11,16 +11,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fft3d.h"
-#include "kernels_fp32.hpp"
-#include "registry.hpp"
-#include "sched.hpp"
+#include "plan_internal.hpp"
 
-using namespace fft3d;
+namespace fft3d {
 
 namespace {
-
 thread_local int g_last_error = FFT3D_OK;
+}  // namespace
 
 enum Scheme {
     kCube = 0,    // whole grid per workgroup
@@ -35,10 +32,8 @@ int set_error(int code)
     return code;
 }
 
-// Twiddle table of a length-n transform with exponent sign `sign`, in the
-// layout described in sched.hpp.  Angles are reduced to an integer index
-// modulo the root order before cos/sin (double precision), then rounded once
-// to float.
+// Angles are reduced to an integer index modulo the root order before
+// cos/sin (double precision), then rounded once to float.
 std::vector<float2> twiddles(int n, int sign)
 {
     const Sched sc = make_sched(n);
@@ -62,42 +57,14 @@ bool env_flag(const char* name)
     return e && e[0] == '1';
 }
 
-bool test_fail_alloc() { return env_flag("FFT3D_TEST_FAIL_ALLOC"); }
+static bool test_fail_alloc() { return env_flag("FFT3D_TEST_FAIL_ALLOC"); }
 
-}  // namespace
+int last_error_value() { return g_last_error; }
+void clear_error() { g_last_error = FFT3D_OK; }
 
-namespace {
+}  // namespace fft3d
 
-// One kernel launch of an exec.  The first pass reads the caller's input,
-// every later pass works in place on the output buffer.
-struct Pass {
-    enum Kind { kCubeK, kPlaneK, kPlanePfK, kRowK, kStrK, kFusedK } kind;
-    int n;        // transform length of this pass
-    long count;   // grids / planes / rows (cube, plane, row kinds)
-    AxisMap map;  // strided kind
-    long tw;      // offset of this pass's twiddle table in d_tw
-    int grid;     // workgroups of a persistent launch
-};
-
-}  // namespace
-
-struct fft3d_plan_s {
-    int nx, ny, nz, batch, precision, direction;
-    int scheme;
-    int device;
-    float2* d_tw;           // all tables of the plan, one allocation
-    long tw_x, tw_y, tw_z;  // offsets (elements) of each dimension's table
-    long tw_rx, tw_ry, tw_rz;  // the same tables for the opposite sign
-    long vol;
-    double* partials;       // energy: one FP64 partial per z-pass workgroup (nx == ny plans)
-    long n_partials;
-    int pf_grid;            // workgroups of the persistent plane pass (nx == ny plans)
-    std::vector<Pass> passes;
-    FusedCtl* ctl;   // persistent-kernel control block (kFused)
-    int fused_grid;  // workgroups of the persistent launch
-    int fused_lag;   // dependency lag in grids
-    int fused_chunk; // items per queue claim (0: static round robin)
-};
+using namespace fft3d;
 
 extern "C" {
 
@@ -117,11 +84,11 @@ const char* fft3d_strerror(int code)
     }
 }
 
-int fft3d_last_error(void) { return g_last_error; }
+int fft3d_last_error(void) { return last_error_value(); }
 
 fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int direction)
 {
-    g_last_error = FFT3D_OK;
+    clear_error();
     if (nx < 1 || ny < 1 || nz < 1 || batch < 1) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
     if (precision != FFT3D_FP32 && precision != FFT3D_FP16_SCALED && precision != FFT3D_BF16_SCALED) {
         set_error(FFT3D_E_INVALID_ARG);
@@ -253,6 +220,9 @@ int fft3d_destroy(fft3d_plan_t p)
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->ctl) (void)hipFree(p->ctl);
     if (p->partials) (void)hipFree(p->partials);
+    if (p->mp.d_grids) (void)hipFree(p->mp.d_grids);
+    if (p->mp.d_items) (void)hipFree(p->mp.d_items);
+    if (p->mp.d_twoff) (void)hipFree(p->mp.d_twoff);
     delete p;
     return FFT3D_OK;
 }
@@ -260,6 +230,12 @@ int fft3d_destroy(fft3d_plan_t p)
 size_t fft3d_buffer_bytes(fft3d_plan_t p)
 {
     if (!p) return 0;
+    if (p->many) {
+        size_t b = 0;
+        for (int g = 0; g < p->mp.ngroups; ++g)
+            b += (size_t)p->mp.batch[g] * p->mp.n[g] * p->mp.n[g] * p->mp.n[g] * sizeof(float2);
+        return b;
+    }
     return (size_t)p->batch * (size_t)p->vol * sizeof(float2);
 }
 
@@ -292,6 +268,7 @@ int fft3d_exec(fft3d_plan_t p, const void* in, void* out, fft3d_stream_t stream)
 {
     const int rc = check_ptrs(p, in, out);
     if (rc != FFT3D_OK) return rc;
+    if (p->many) return FFT3D_E_INVALID_ARG;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const float2* src = static_cast<const float2*>(in);
     float2* dst = static_cast<float2*>(out);
@@ -310,6 +287,7 @@ int fft3d_exec(fft3d_plan_t p, const void* in, void* out, fft3d_stream_t stream)
 int fft3d_plan_passes(fft3d_plan_t p)
 {
     if (!p) return FFT3D_E_INVALID_ARG;
+    if (p->many) return 1;
     return (int)p->passes.size();
 }
 
@@ -317,7 +295,7 @@ int fft3d_exec_pass(fft3d_plan_t p, int pass, const void* in, void* out, fft3d_s
 {
     const int rc = check_ptrs(p, in, out);
     if (rc != FFT3D_OK) return rc;
-    if (pass < 0 || pass >= (int)p->passes.size()) return FFT3D_E_INVALID_ARG;
+    if (p->many || pass < 0 || pass >= (int)p->passes.size()) return FFT3D_E_INVALID_ARG;
     const hipError_t e = run_pass(p, p->passes[pass], static_cast<const float2*>(in), static_cast<float2*>(out),
                                   reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) {
@@ -349,7 +327,7 @@ static int energy_args(fft3d_plan_t p, const void* a, const void* b, const void*
     if (!p || !a || !b || !V || !d) return FFT3D_E_INVALID_ARG;
     if (((uintptr_t)a % 16) || ((uintptr_t)b % 16) || ((uintptr_t)V % 16) || ((uintptr_t)d % 8))
         return FFT3D_E_ALIGNMENT;
-    if (p->precision != FFT3D_FP32 || p->nx != p->ny || !p->partials) return FFT3D_E_UNSUPPORTED;
+    if (p->many || p->precision != FFT3D_FP32 || p->nx != p->ny || !p->partials) return FFT3D_E_UNSUPPORTED;
     return FFT3D_OK;
 }
 
@@ -407,9 +385,12 @@ int fft3d_plan_check(fft3d_plan_t p)
     return FFT3D_OK;
 }
 
+int many_describe(fft3d_plan_t p, char* buf, size_t len);
+
 int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
 {
     if (!p) return FFT3D_E_INVALID_ARG;
+    if (p->many) return many_describe(p, buf, len);
     auto radices = [](int n) {
         const Sched sc = make_sched(n);
         std::string s;

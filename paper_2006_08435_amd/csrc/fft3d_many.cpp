@@ -1,0 +1,392 @@
+// Heterogeneous batches: fft3d_plan_many / fft3d_exec_many, the work-list
+// builder and the schedule autotuner with its JSON cache.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <fstream>
+#include <map>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include <sys/stat.h>
+
+#include "plan_internal.hpp"
+
+using namespace fft3d;
+
+namespace {
+
+int device_cus(int dev)
+{
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    return cus;
+}
+
+// Work list: for every grid its plane items, and its slab items at least
+// `lag` list positions after its last plane item.
+std::vector<unsigned> build_items(const std::vector<ManyGrid>& grids, int threads, long lag)
+{
+    std::vector<unsigned> out;
+    std::deque<std::pair<long, int>> ready;   // (list length when the planes ended, grid)
+    auto emit_slabs = [&](int g) {
+        const int n = grids[g].n, per = many_per_item(n, threads);
+        for (int i = 0; i < n; i += per) out.push_back(many_item((unsigned)g, 1u, (unsigned)i));
+    };
+    auto flush = [&]() {
+        while (!ready.empty() && (long)out.size() - ready.front().first >= lag) {
+            emit_slabs(ready.front().second);
+            ready.pop_front();
+        }
+    };
+    for (int g = 0; g < (int)grids.size(); ++g) {
+        const int n = grids[g].n, per = many_per_item(n, threads);
+        for (int i = 0; i < n; i += per) {
+            out.push_back(many_item((unsigned)g, 0u, (unsigned)i));
+            flush();
+        }
+        ready.push_back({(long)out.size(), g});
+    }
+    while (!ready.empty()) {
+        emit_slabs(ready.front().second);
+        ready.pop_front();
+    }
+    return out;
+}
+
+size_t plan_lds(const ManyPlan& mp, int threads)
+{
+    size_t m = 0;
+    for (int g = 0; g < mp.ngroups; ++g) {
+        const size_t b = many_lds_bytes(mp.n[g], threads);
+        m = b > m ? b : m;
+    }
+    return m;
+}
+
+// Apply a (threads, chunk) schedule: occupancy, grid, work list.
+int apply_schedule(fft3d_plan_s* p, int threads, int chunk)
+{
+    ManyPlan& mp = p->mp;
+    const size_t lds = plan_lds(mp, threads);
+    const int per_cu = many_blocks_per_cu(threads, lds);
+    if (per_cu < 1) return FFT3D_E_UNSUPPORTED;
+    const int resident = per_cu * device_cus(p->device);
+    const long lag = (long)resident * chunk + resident;
+    std::vector<unsigned> items = build_items(mp.grids, threads, lag);
+    if ((long)items.size() > mp.items_cap) return FFT3D_E_INVALID_ARG;
+    if (hipMemcpy(mp.d_items, items.data(), items.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    mp.nitems = (long)items.size();
+    mp.threads = threads;
+    mp.chunk = chunk;
+    mp.lds = lds;
+    const long claims = (mp.nitems + chunk - 1) / chunk;
+    mp.grid = (int)(claims < resident ? claims : resident);
+    return FFT3D_OK;
+}
+
+ManyArgs make_args(const fft3d_plan_s* p, const void* const* in, void* const* out)
+{
+    ManyArgs a{};
+    for (int g = 0; g < p->mp.ngroups; ++g) {
+        a.in[g] = static_cast<const float2*>(in[g]);
+        a.out[g] = static_cast<float2*>(out[g]);
+    }
+    a.grids = p->mp.d_grids;
+    a.items = p->mp.d_items;
+    a.nitems = p->mp.nitems;
+    a.tw = p->d_tw;
+    a.tw_off = p->mp.d_twoff;
+    a.ctl = p->ctl;
+    a.chunk = p->mp.chunk;
+    a.ngrids = (int)p->mp.grids.size();
+    return a;
+}
+
+// ----------------------------------------------------------- tuning cache --
+
+std::string cache_path()
+{
+    if (const char* e = std::getenv("FFT3D_TUNE_CACHE")) return e;
+    const char* h = std::getenv("HOME");
+    return std::string(h ? h : "/tmp") + "/.cache/fft3d/tune.json";
+}
+
+std::string cache_key(const fft3d_plan_s* p)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    std::ostringstream k;
+    k << arch << "|many|" << p->direction << "|";
+    for (int g = 0; g < p->mp.ngroups; ++g) k << (g ? "," : "") << p->mp.n[g] << "x" << p->mp.batch[g];
+    return k.str();
+}
+
+// The cache file holds one entry per line:  "key": {"threads": T, "chunk": K, "ms": t},
+// Lines that do not parse are ignored (a corrupt file means "no entries").
+std::map<std::string, std::string> cache_read()
+{
+    std::map<std::string, std::string> m;
+    std::ifstream f(cache_path());
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t a = line.find('"'), b = a == std::string::npos ? a : line.find('"', a + 1);
+        const size_t c = b == std::string::npos ? b : line.find('{', b);
+        const size_t d = c == std::string::npos ? c : line.find('}', c);
+        if (d == std::string::npos) continue;
+        m[line.substr(a + 1, b - a - 1)] = line.substr(c, d - c + 1);
+    }
+    return m;
+}
+
+bool cache_lookup(const std::string& key, int& threads, int& chunk)
+{
+    const auto m = cache_read();
+    const auto it = m.find(key);
+    if (it == m.end()) return false;
+    int t = 0, c = 0;
+    double ms = 0;
+    if (std::sscanf(it->second.c_str(), "{\"threads\": %d, \"chunk\": %d, \"ms\": %lf}", &t, &c, &ms) != 3) return false;
+    if ((t != 512 && t != 1024) || c < 1 || c > 64) return false;
+    threads = t;
+    chunk = c;
+    return true;
+}
+
+void cache_store(const std::string& key, int threads, int chunk, double ms)
+{
+    auto m = cache_read();
+    char v[128];
+    std::snprintf(v, sizeof v, "{\"threads\": %d, \"chunk\": %d, \"ms\": %.5f}", threads, chunk, ms);
+    m[key] = v;
+    const std::string path = cache_path();
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        std::string dir = path.substr(0, slash), cur;
+        std::stringstream ss(dir);
+        std::string part;
+        while (std::getline(ss, part, '/')) {
+            cur += part + "/";
+            (void)mkdir(cur.c_str(), 0755);
+        }
+    }
+    std::ofstream f(path + ".tmp");
+    f << "{\n";
+    size_t i = 0;
+    for (const auto& kv : m) f << "\"" << kv.first << "\": " << kv.second << (++i < m.size() ? ",\n" : "\n");
+    f << "}\n";
+    f.close();
+    std::rename((path + ".tmp").c_str(), path.c_str());
+}
+
+// Time every (threads, chunk) candidate on scratch buffers; keep the fastest.
+int tune(fft3d_plan_s* p)
+{
+    ManyPlan& mp = p->mp;
+    std::vector<void*> bufs(mp.ngroups, nullptr);
+    int rc = FFT3D_OK;
+    for (int g = 0; g < mp.ngroups && rc == FFT3D_OK; ++g) {
+        const size_t b = (size_t)mp.batch[g] * mp.n[g] * mp.n[g] * mp.n[g] * sizeof(float2);
+        if (hipMalloc(&bufs[g], b) != hipSuccess || hipMemset(bufs[g], 0, b) != hipSuccess) rc = FFT3D_E_ALLOC;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == FFT3D_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = FFT3D_E_LAUNCH;
+    double best = 1e30;
+    int bt = mp.threads, bc = mp.chunk;
+    const int cand_t[] = {1024, 512};
+    const int cand_c[] = {1, 2, 4, 8};
+    for (int t : cand_t)
+        for (int c : cand_c) {
+            if (rc != FFT3D_OK) break;
+            if (apply_schedule(p, t, c) != FFT3D_OK) continue;
+            const ManyArgs a = make_args(p, (const void* const*)bufs.data(), bufs.data());
+            bool ok = true;
+            for (int w = 0; w < 2 && ok; ++w) ok = launch_many(a, p->direction, t, mp.grid, mp.lds, nullptr) == hipSuccess;
+            ok = ok && hipEventRecord(e0, nullptr) == hipSuccess;
+            for (int r = 0; r < 5 && ok; ++r) ok = launch_many(a, p->direction, t, mp.grid, mp.lds, nullptr) == hipSuccess;
+            ok = ok && hipEventRecord(e1, nullptr) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            float ms = 0.f;
+            if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms / 5 < best) {
+                best = ms / 5;
+                bt = t;
+                bc = c;
+            }
+            if (!ok) (void)hipGetLastError();
+        }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (rc != FFT3D_OK) return rc;
+    rc = apply_schedule(p, bt, bc);
+    if (rc == FFT3D_OK) {
+        mp.tuned = true;
+        mp.tuned_ms = best;
+        cache_store(cache_key(p), bt, bc, best);
+    }
+    return rc;
+}
+
+void free_plan(fft3d_plan_s* p)
+{
+    if (!p) return;
+    if (p->d_tw) (void)hipFree(p->d_tw);
+    if (p->ctl) (void)hipFree(p->ctl);
+    if (p->mp.d_grids) (void)hipFree(p->mp.d_grids);
+    if (p->mp.d_items) (void)hipFree(p->mp.d_items);
+    if (p->mp.d_twoff) (void)hipFree(p->mp.d_twoff);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+fft3d_plan_t fft3d_plan_many(int count, const int* nx, const int* ny, const int* nz, const int* batch, int precision,
+                             int direction)
+{
+    clear_error();
+    if (count < 1 || count > kMaxGroups || !nx || !ny || !nz || !batch) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
+    if (precision != FFT3D_FP32 && precision != FFT3D_FP16_SCALED && precision != FFT3D_BF16_SCALED) {
+        set_error(FFT3D_E_INVALID_ARG);
+        return nullptr;
+    }
+    if (direction != FFT3D_FORWARD && direction != FFT3D_INVERSE) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
+    long total = 0, ngrids = 0;
+    for (int g = 0; g < count; ++g) {
+        if (nx[g] < 1 || ny[g] < 1 || nz[g] < 1 || batch[g] < 1) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
+        if (!size_supported(nx[g]) || !size_supported(ny[g]) || !size_supported(nz[g])) {
+            set_error(FFT3D_E_UNSUPPORTED_SIZE);
+            return nullptr;
+        }
+        if (nx[g] != ny[g] || ny[g] != nz[g] || !many_size_ok(nx[g])) { set_error(FFT3D_E_UNSUPPORTED); return nullptr; }
+        total += (long)batch[g] * nx[g] * nx[g] * nx[g];
+        ngrids += batch[g];
+    }
+    if (total > (1L << 36) || ngrids > (1L << 23)) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
+    if (precision != FFT3D_FP32) { set_error(FFT3D_E_UNSUPPORTED); return nullptr; }
+    int ndev = 0, dev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1 || hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(FFT3D_E_NO_DEVICE);
+        return nullptr;
+    }
+    fft3d_plan_s* p = new (std::nothrow) fft3d_plan_s{};
+    if (!p) { set_error(FFT3D_E_ALLOC); return nullptr; }
+    p->many = true;
+    p->precision = precision;
+    p->direction = direction;
+    p->device = dev;
+    p->batch = (int)ngrids;
+    p->nx = p->ny = p->nz = nx[0];
+    p->vol = total / (ngrids ? ngrids : 1);
+    ManyPlan& mp = p->mp;
+    mp.ngroups = count;
+    std::vector<float2> tab;
+    std::vector<int> twoff(129, 0);
+    for (int g = 0; g < count; ++g) {
+        mp.n[g] = nx[g];
+        mp.batch[g] = batch[g];
+        for (int b = 0; b < batch[g]; ++b) mp.grids.push_back({nx[g], g, (long)b * nx[g] * nx[g] * nx[g]});
+        bool seen = false;
+        for (int h = 0; h < g; ++h) seen = seen || mp.n[h] == nx[g];
+        if (!seen) {
+            twoff[nx[g]] = (int)tab.size();
+            const std::vector<float2> t = twiddles(nx[g], direction);
+            tab.insert(tab.end(), t.begin(), t.end());
+            if (tab.size() % 2) tab.push_back(make_float2(0.f, 0.f));
+        }
+    }
+    if (tab.empty()) tab.push_back(make_float2(0.f, 0.f));
+    // capacity: one item per plane and slab at the smallest per-item count
+    long cap = 0;
+    for (const ManyGrid& gd : mp.grids) cap += 2L * gd.n;
+    mp.items_cap = cap;
+    const size_t cb = sizeof(FusedCtl) + sizeof(unsigned) * (size_t)ngrids;
+    bool ok = !env_flag("FFT3D_TEST_FAIL_ALLOC") && hipMalloc((void**)&p->d_tw, tab.size() * sizeof(float2)) == hipSuccess &&
+              hipMalloc((void**)&mp.d_grids, mp.grids.size() * sizeof(ManyGrid)) == hipSuccess &&
+              hipMalloc((void**)&mp.d_items, cap * sizeof(unsigned)) == hipSuccess &&
+              hipMalloc((void**)&mp.d_twoff, twoff.size() * sizeof(int)) == hipSuccess &&
+              hipMalloc((void**)&p->ctl, cb) == hipSuccess;
+    ok = ok && hipMemcpy(p->d_tw, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(mp.d_grids, mp.grids.data(), mp.grids.size() * sizeof(ManyGrid), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(mp.d_twoff, twoff.data(), twoff.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemset(p->ctl, 0, cb) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_plan(p);
+        set_error(FFT3D_E_ALLOC);
+        return nullptr;
+    }
+    int threads = 1024, chunk = 2;
+    const bool cached = cache_lookup(cache_key(p), threads, chunk);
+    int rc = apply_schedule(p, threads, chunk);
+    if (rc == FFT3D_OK && !cached && env_flag("FFT3D_TUNE")) rc = tune(p);
+    if (rc != FFT3D_OK) {
+        free_plan(p);
+        set_error(rc);
+        return nullptr;
+    }
+    mp.tuned = mp.tuned || cached;
+    return p;
+}
+
+int fft3d_exec_many(fft3d_plan_t p, const void* const* in, void* const* out, fft3d_stream_t stream)
+{
+    if (!p || !in || !out) return FFT3D_E_INVALID_ARG;
+    if (!p->many) return FFT3D_E_INVALID_ARG;
+    for (int g = 0; g < p->mp.ngroups; ++g) {
+        if (!in[g] || !out[g]) return FFT3D_E_INVALID_ARG;
+        if (((uintptr_t)in[g] % 16) || ((uintptr_t)out[g] % 16)) return FFT3D_E_ALIGNMENT;
+    }
+    const ManyArgs a = make_args(p, in, out);
+    if (launch_many(a, p->direction, p->mp.threads, p->mp.grid, p->mp.lds, reinterpret_cast<hipStream_t>(stream)) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
+int fft3d_plan_set_schedule(fft3d_plan_t p, int threads, int chunk)
+{
+    if (!p || !p->many || (threads != 512 && threads != 1024) || chunk < 1 || chunk > 64) return FFT3D_E_INVALID_ARG;
+    return apply_schedule(p, threads, chunk);
+}
+
+int fft3d_plan_tune(fft3d_plan_t p)
+{
+    if (!p || !p->many) return FFT3D_E_INVALID_ARG;
+    return tune(p);
+}
+
+int many_describe(fft3d_plan_t p, char* buf, size_t len)
+{
+    std::ostringstream d;
+    d << "many groups=";
+    for (int g = 0; g < p->mp.ngroups; ++g) d << (g ? "," : "") << p->mp.n[g] << "^3x" << p->mp.batch[g];
+    d << " threads=" << p->mp.threads << " chunk=" << p->mp.chunk << " workgroups=" << p->mp.grid
+      << " lds=" << p->mp.lds << " items=" << p->mp.nitems << (p->mp.tuned ? " tuned" : " default")
+      << (p->direction < 0 ? " forward" : " inverse") << " kernels=k_many";
+    const std::string s = d.str();
+    if (buf && len) {
+        std::strncpy(buf, s.c_str(), len - 1);
+        buf[len - 1] = 0;
+    }
+    return (int)s.size();
+}
+
+}  // extern "C"

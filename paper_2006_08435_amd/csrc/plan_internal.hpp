@@ -1,0 +1,74 @@
+// Internal plan state shared by the C-ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fft3d.h"
+#include "kernels_fp32.hpp"
+#include "kernels_many.hpp"
+#include "registry.hpp"
+#include "sched.hpp"
+
+namespace fft3d {
+
+int set_error(int code);
+int last_error_value();
+void clear_error();
+bool env_flag(const char* name);
+// Twiddle table of a length-n transform for exponent sign `sign` (sched.hpp layout).
+std::vector<float2> twiddles(int n, int sign);
+
+// One kernel launch of an exec.  The first pass reads the caller's input,
+// every later pass works in place on the output buffer.
+struct Pass {
+    enum Kind { kCubeK, kPlaneK, kPlanePfK, kRowK, kStrK, kFusedK } kind;
+    int n;        // transform length of this pass
+    long count;   // grids / planes / rows (cube, plane, row kinds)
+    AxisMap map;  // strided kind
+    long tw;      // offset of this pass's twiddle table in d_tw
+    int grid;     // workgroups of a persistent launch
+};
+
+// Heterogeneous batch (fft3d_plan_many): groups of cubic grids, one
+// persistent launch over a host-built work list.
+struct ManyPlan {
+    int ngroups = 0;
+    int n[kMaxGroups] = {};
+    int batch[kMaxGroups] = {};
+    std::vector<ManyGrid> grids;
+    ManyGrid* d_grids = nullptr;
+    unsigned* d_items = nullptr;
+    long nitems = 0;
+    long items_cap = 0;
+    int* d_twoff = nullptr;
+    int threads = 1024;
+    int chunk = 2;
+    int grid = 1;
+    size_t lds = 0;
+    bool tuned = false;
+    double tuned_ms = 0.0;
+};
+
+}  // namespace fft3d
+
+struct fft3d_plan_s {
+    int nx, ny, nz, batch, precision, direction;
+    int scheme;
+    int device;
+    float2* d_tw;              // all tables of the plan, one allocation
+    long tw_x, tw_y, tw_z;     // offsets (elements) of each dimension's table
+    long tw_rx, tw_ry, tw_rz;  // the same tables for the opposite sign
+    long vol;
+    double* partials;          // energy: one FP64 partial per z-pass workgroup (nx == ny plans)
+    long n_partials;
+    int pf_grid;               // workgroups of the persistent plane pass (nx == ny plans)
+    std::vector<fft3d::Pass> passes;
+    fft3d::FusedCtl* ctl;      // persistent-kernel control block (fused / many)
+    int fused_grid;            // workgroups of the persistent launch
+    int fused_lag;             // dependency lag in grids
+    int fused_chunk;           // items per queue claim (0: static round robin)
+    bool many;                 // plan from fft3d_plan_many
+    fft3d::ManyPlan mp;
+};

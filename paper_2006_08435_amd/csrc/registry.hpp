@@ -8,6 +8,7 @@ namespace fft3d {
 
 struct AxisMap;
 struct FusedCtl;
+struct ManyArgs;
 
 using CubeFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long grids, hipStream_t st);
 using PlaneFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, hipStream_t st);
@@ -39,6 +40,13 @@ AxisRowFn axis_row_fn(int n, int sign);
 FusedFn fused_fn(int n, int sign);
 // Workgroups of the fused kernel that fit on one compute unit at once.
 int fused_blocks_per_cu(int n);
+
+// Heterogeneous persistent kernel (kernels_many.hpp); threads is 512 or 1024.
+hipError_t launch_many(const ManyArgs& a, int sign, int threads, int grid, size_t lds_bytes, hipStream_t st);
+int many_blocks_per_cu(int threads, size_t lds_bytes);
+bool many_size_ok(int n);
+size_t many_lds_bytes(int n, int threads);   // dynamic LDS one size-n item needs
+int many_per_item(int n, int threads);       // planes (slabs) per work item
 
 // Kernel geometry (threads, LDS bytes) for diagnostics.
 struct KernelInfo {

@@ -87,3 +87,30 @@ def test_python_layer_raises_without_device():
     import paper_2006_08435_amd as fft3d
     with pytest.raises(fft3d.Fft3dError):
         fft3d.Plan(16, 16, 16)
+
+
+def test_plan_many_rejects_bad_arguments():
+    import ctypes
+    L = _lib()
+    lib = L.lib()
+
+    def call(ns, bs, prec=0, direction=-1, count=None):
+        k = len(ns)
+        a = (ctypes.c_int * max(k, 1))(*ns)
+        b = (ctypes.c_int * max(k, 1))(*bs)
+        p = lib.fft3d_plan_many(k if count is None else count, ctypes.cast(a, ctypes.c_void_p),
+                                ctypes.cast(a, ctypes.c_void_p), ctypes.cast(a, ctypes.c_void_p),
+                                ctypes.cast(b, ctypes.c_void_p), prec, direction)
+        assert not p
+        return lib.fft3d_last_error()
+
+    assert call([64], [1], count=0) == L.FFT3D_E_INVALID_ARG
+    assert call([64] * 17, [1] * 17) == L.FFT3D_E_INVALID_ARG
+    assert call([64], [0]) == L.FFT3D_E_INVALID_ARG
+    assert call([64], [1], prec=5) == L.FFT3D_E_INVALID_ARG
+    assert call([64], [1], direction=0) == L.FFT3D_E_INVALID_ARG
+    assert call([7], [1]) == L.FFT3D_E_UNSUPPORTED_SIZE
+    assert call([16], [1]) == L.FFT3D_E_UNSUPPORTED       # not a persistent-kernel size
+    assert call([64], [1], prec=1) == L.FFT3D_E_UNSUPPORTED
+    assert lib.fft3d_exec_many(None, None, None, None) == L.FFT3D_E_INVALID_ARG
+    assert lib.fft3d_plan_set_schedule(None, 1024, 2) == L.FFT3D_E_INVALID_ARG

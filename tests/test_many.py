@@ -1,0 +1,167 @@
+"""Batched/mixed form: heterogeneous grids in one persistent launch."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 5e-6
+SCHEDULES = [(t, c) for t in (1024, 512) for c in (1, 2, 4, 8)]
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128).ravel()
+    b = np.asarray(b, np.complex128).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def F(tmp_path_factory):
+    import paper_2006_08435_amd as m
+    # keep tuning-cache lookups away from the user's home cache
+    os.environ["FFT3D_TUNE_CACHE"] = str(tmp_path_factory.mktemp("tc") / "tune.json")
+    return m
+
+
+def inputs(groups, seed0):
+    out = []
+    for g, (n, b) in enumerate(groups):
+        out.append(np.stack([workloads.sphere_grid(n, seed0 + 97 * g + j) for j in range(b)]))
+    return out
+
+
+def run(plan, xs):
+    ins = [torch.from_numpy(x).cuda() for x in xs]
+    outs = plan.exec(ins)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs]
+
+
+@pytest.mark.parametrize("direction", [-1, 1])
+def test_mixed_small_groups_match_oracle(F, direction):
+    groups = [(64, 5), (48, 2), (32, 3), (100, 1), (24, 4)]
+    xs = inputs(groups, 11)
+    plan = F.PlanMany(groups, direction)
+    got = run(plan, xs)
+    for (n, b), x, y in zip(groups, xs, got):
+        for j in range(b):
+            ref = oracle.fft3d(x[j].astype(np.complex128), direction)
+            assert rel(y[j], ref) <= TOL, (n, j)
+    from paper_2006_08435_amd import _lib
+    assert _lib.lib().fft3d_plan_check(plan.handle) == 0
+
+
+def test_every_schedule_gives_identical_results(F):
+    groups = [(64, 3), (72, 1), (48, 2), (128, 1)]
+    xs = inputs(groups, 5)
+    plan = F.PlanMany(groups, -1)
+    ref = None
+    for t, c in SCHEDULES:
+        plan.set_schedule(t, c)
+        got = run(plan, xs)
+        if ref is None:
+            ref = got
+            for (n, b), x, y in zip(groups, xs, got):
+                assert rel(y[0], oracle.fft3d(x[0].astype(np.complex128), -1)) <= TOL
+        else:
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), (t, c)
+    from paper_2006_08435_amd import _lib
+    assert _lib.lib().fft3d_plan_check(plan.handle) == 0
+
+
+def test_matches_plain_per_grid_execs(F):
+    groups = [(96, 2), (60, 3)]
+    xs = inputs(groups, 21)
+    plan = F.PlanMany(groups, 1)
+    got = run(plan, xs)
+    for (n, b), x, y in zip(groups, xs, got):
+        for j in range(b):
+            plain = F.ifftn(torch.from_numpy(x[j]).cuda()).cpu().numpy()
+            assert rel(y[j], plain) <= 1e-6
+
+
+def test_inplace_and_repeat(F):
+    groups = [(64, 6), (48, 3)]
+    xs = inputs(groups, 31)
+    plan = F.PlanMany(groups, -1)
+    first = run(plan, xs)
+    ins = [torch.from_numpy(x).cuda() for x in xs]
+    for _ in range(10):
+        bufs = [t.clone() for t in ins]
+        plan.exec(bufs, bufs)
+    torch.cuda.synchronize()
+    for a, b in zip(first, bufs):
+        assert np.array_equal(a, b.cpu().numpy())
+
+
+def test_graph_capture_replays_match_eager(F):
+    groups = [(64, 4), (80, 1), (36, 2)]
+    xs = inputs(groups, 41)
+    plan = F.PlanMany(groups, -1)
+    ins = [torch.from_numpy(x).cuda() for x in xs]
+    eager = [o.clone() for o in plan.exec(ins)]
+    outs = [torch.empty_like(t) for t in ins]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.exec(ins, outs, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for r in range(5):
+        for o in outs:
+            o.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(eager, outs):
+            assert torch.equal(a, b), r
+        plan.exec(ins)              # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_tuner_and_cache(F, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("FFT3D_TUNE_CACHE", str(cache))
+    monkeypatch.setenv("FFT3D_TUNE", "1")
+    groups = [(64, 4), (48, 1)]
+    p1 = F.PlanMany(groups, -1)
+    assert "tuned" in p1.describe()
+    d = json.loads(cache.read_text())
+    (key, val), = d.items()
+    assert val["threads"] in (512, 1024) and 1 <= val["chunk"] <= 8 and val["ms"] > 0
+    monkeypatch.delenv("FFT3D_TUNE")
+    p2 = F.PlanMany(groups, -1)            # read back from the cache
+    assert "tuned" in p2.describe()
+    assert "threads=%d chunk=%d" % (val["threads"], val["chunk"]) in p2.describe()
+    cache.write_text("{ this is not json")  # a corrupt cache falls back to the default
+    p3 = F.PlanMany(groups, -1)
+    assert "default" in p3.describe()
+    xs = inputs(groups, 51)
+    for a, b in zip(run(p1, xs), run(p3, xs)):
+        assert np.array_equal(a, b)
+
+
+def test_mixed_grid_workload(F):
+    """256 grids of 64^3 plus one each of 48^3, 72^3, 96^3, 100^3, 120^3."""
+    groups = [(64, 256)] + [(n, 1) for n in workloads.MIXED_SIZES]
+    xs = [np.stack([workloads.sphere_grid(64, workloads.SEED_BATCH64 + j) for j in range(256)])]
+    xs += [workloads.sphere_grid(n, workloads.SEED_MIXED + n)[None] for n in workloads.MIXED_SIZES]
+    plan = F.PlanMany(groups, 1)
+    got = run(plan, xs)
+    worst = 0.0
+    for (n, b), x, y in zip(groups, xs, got):
+        for j in ([0, 77, 255] if b > 1 else [0]):
+            r = rel(y[j], oracle.fft3d(x[j].astype(np.complex128), 1))
+            worst = max(worst, r)
+    assert worst <= TOL, worst
+    # every 64^3 grid: Parseval against its input
+    e_in = np.sum(np.abs(xs[0].astype(np.complex128)) ** 2, axis=(1, 2, 3))
+    e_out = np.sum(np.abs(got[0].astype(np.complex128)) ** 2, axis=(1, 2, 3))
+    assert np.all(np.abs(e_out - 64 ** 3 * e_in) <= 1e-5 * 64 ** 3 * e_in)
