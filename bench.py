@@ -33,6 +33,7 @@ WORKLOADS = {
     "single64": (64, 1, 2064, "c2c 3D FFT, one 64^3 grid, inverse then forward, complex64"),
     "batch64": (64, 256, 4000, "c2c 3D FFT, 256 grids of 64^3, inverse then forward, complex64"),
 }
+EXTRA_WORKLOADS = ("mixed", "energy96", "fp16_128", "bf16_128")
 
 
 def source_hash() -> str:
@@ -73,7 +74,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="batch128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="batch128", choices=sorted(WORKLOADS) + list(EXTRA_WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -89,6 +90,12 @@ def main(argv=None):
     import paper_2006_08435_amd as fft3d
     from paper_2006_08435_amd import _lib
 
+    if args.workload == "mixed":
+        return bench_mixed(args)
+    if args.workload == "energy96":
+        return bench_energy(args)
+    if args.workload in ("fp16_128", "bf16_128"):
+        return bench_q16(args, args.workload[:4])
     n, batch, seed0, desc = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -208,6 +215,268 @@ def main(argv=None):
     }
     print(json.dumps(out))
     return 0
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _time(fn, steps, warmup, stream):
+    """Average ms of fn() over `steps` calls, HIP events on `stream`."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _base_record(metric_value, unit, args, ms, desc, config, dtype="f32"):
+    return {"metric": "3D FFT GFLOP/s (5N^3log2N^3/t) + HBM GB/s vs plain FP32, at rel-L2 err vs FP64",
+            "value": round(metric_value, 1), "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": dict({"workload": desc}, **config)}
+
+
+def bench_mixed(args):
+    """256 x 64^3 plus one each of 48^3, 72^3, 96^3, 100^3, 120^3 (inverse):
+    one persistent launch (replayed from a captured graph) against per-grid
+    and per-group plain launches."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2006_08435_amd as fft3d
+    import workloads
+    groups = [(64, 256)] + [(n, 1) for n in workloads.MIXED_SIZES]
+    xs = [np.stack([workloads.sphere_grid(64, workloads.SEED_BATCH64 + j) for j in range(256)])]
+    xs += [workloads.sphere_grid(n, workloads.SEED_MIXED + n)[None] for n in workloads.MIXED_SIZES]
+    ins = [torch.from_numpy(x).cuda() for x in xs]
+    outs = [torch.empty_like(t) for t in ins]
+    stream = torch.cuda.current_stream()
+    plan = fft3d.PlanMany(groups, fft3d.FFT3D_INVERSE)
+    if os.environ.get("FFT3D_BENCH_TUNE") == "1":
+        plan.tune()
+    sh = int(stream.cuda_stream)
+    iptr, optr = [t.data_ptr() for t in ins], [t.data_ptr() for t in outs]
+    eager_ms = _time(lambda: plan.exec_ptrs(iptr, optr, sh), args.steps, args.warmup, stream)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(stream)
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.exec_ptrs(iptr, optr, int(s.cuda_stream))
+    stream.wait_stream(s)
+    graph_ms = _time(g.replay, args.steps, args.warmup, stream)
+    # per-grid plain launches (261 fft3d_exec calls) and per-group batched launches
+    singles = {n: fft3d.Plan(n, n, n, 1, "fp32", fft3d.FFT3D_INVERSE) for n, _ in groups}
+    per_grid = []
+    for (n, b), i, o in zip(groups, ins, outs):
+        for j in range(b):
+            per_grid.append((singles[n], i.data_ptr() + j * n ** 3 * 8, o.data_ptr() + j * n ** 3 * 8))
+    grid_ms = _time(lambda: [p.exec_ptr(a, b, sh) for p, a, b in per_grid], max(3, args.steps // 5), 2, stream)
+    batched = [(fft3d.Plan(n, n, n, b, "fp32", fft3d.FFT3D_INVERSE), i.data_ptr(), o.data_ptr())
+               for (n, b), i, o in zip(groups, ins, outs)]
+    group_ms = _time(lambda: [p.exec_ptr(a, b, sh) for p, a, b in batched], args.steps, args.warmup, stream)
+    g.replay()
+    torch.cuda.synchronize()
+    got = [o.cpu().numpy() for o in outs]
+    worst = 0.0
+    for (n, b), x, y in zip(groups, xs, got):
+        for j in ([0, 255] if b > 1 else [0]):
+            ref = oracle.fft3d(x[j].astype(np.complex128), 1)
+            worst = max(worst, float(np.linalg.norm(y[j] - ref) / np.linalg.norm(ref)))
+    flops = sum(5.0 * n ** 3 * math.log2(n ** 3) * b for n, b in groups)
+    bytes_ = sum(16.0 * n ** 3 * b for n, b in groups)
+    rec = _base_record(flops / (graph_ms * 1e-3) / 1e9, "GFLOP/s", args, graph_ms,
+                       "c2c 3D FFT inverse, 256 grids of 64^3 + one each of 48^3, 72^3, 96^3, 100^3, 120^3, one "
+                       "persistent launch replayed from a HIP graph, complex64",
+                       {"groups": groups, "precision": "fp32", "input": "sphere-cutoff plane-wave coefficients"})
+    achieved = bytes_ / (graph_ms * 1e-3) / 1e9
+    rec.update({
+        "hbm_gbs_algorithmic": round(achieved, 1), "hbm_frac_algorithmic": round(achieved / HBM_PEAK_GBS, 4),
+        "rel_l2_vs_fp64": {"max_over_sampled_grids": worst},
+        "compare_ms": {"persistent_graph": round(graph_ms, 4), "persistent_eager": round(eager_ms, 4),
+                       "per_grid_plain_launches_261": round(grid_ms, 4),
+                       "per_group_batched_launches_6": round(group_ms, 4)},
+        "plans": {"many": plan.describe()},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("mixed", "k_many"),
+                     "kernel": "k_many<1,%s>" % plan.describe().split("threads=")[1].split()[0],
+                     "ms_per_launch": round(graph_ms, 5)},
+        "cpu_baseline": None if args.no_cpu_baseline else _cpu_oracle(xs[0], 64, 1, args.cpu_seconds, "64^3 grids"),
+        "source_hash": source_hash(),
+    })
+    print(json.dumps(rec))
+    return 0
+
+
+def bench_energy(args):
+    """128 orbitals at 96^3: E = sum V |IFFT(c)|^2 (fused) and E + gradient."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2006_08435_amd as fft3d
+    from paper_2006_08435_amd import _lib
+    import workloads
+    B, n = 128, 96
+    c = np.stack([workloads.sphere_grid(n, workloads.SEED_ORBITALS + j) for j in range(B)])
+    V = workloads.smooth_potential(n, workloads.SEED_POTENTIAL)
+    ct = torch.from_numpy(c).cuda()
+    Vt = torch.from_numpy(V).cuda()
+    psi = torch.empty_like(ct)
+    grad = torch.empty_like(ct)
+    E = torch.zeros((), dtype=torch.float64, device="cuda")
+    gE = torch.ones((), dtype=torch.float64, device="cuda")
+    plan = fft3d.Plan(n, n, n, B, "fp32", fft3d.FFT3D_INVERSE)
+    L = _lib.lib()
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+
+    def fwd():
+        _lib.check(L.fft3d_energy_fwd(plan.handle, ct.data_ptr(), Vt.data_ptr(), psi.data_ptr(), E.data_ptr(), sh))
+
+    def bwd(have_psi):
+        src = psi if have_psi else ct
+        _lib.check(L.fft3d_energy_bwd(plan.handle, src.data_ptr(), int(have_psi), Vt.data_ptr(), gE.data_ptr(),
+                                      grad.data_ptr(), sh))
+
+    fwd_ms = _time(fwd, args.steps, args.warmup, stream)
+    both_saved = _time(lambda: (fwd(), bwd(True)), args.steps, args.warmup, stream)
+    both_recomp = _time(lambda: (fwd(), bwd(False)), args.steps, args.warmup, stream)
+    fwd()
+    bwd(True)
+    torch.cuda.synchronize()
+    E_ref, _, g_ref = oracle.energy(c[:8].astype(np.complex128), V.astype(np.float64))
+    # E over all orbitals vs oracle: sum of per-orbital chunks
+    E_all = 0.0
+    for k in range(0, B, 16):
+        e, _, _ = oracle.energy(c[k:k + 16].astype(np.complex128), V.astype(np.float64), want_grad=False)
+        E_all += e
+    g8 = grad[:8].cpu().numpy()
+    flops = 5.0 * n ** 3 * math.log2(n ** 3) * B
+    rec = _base_record(2 * flops / (both_saved * 1e-3) / 1e9, "GFLOP/s", args, both_saved,
+                       "plane-wave local-potential energy E = sum V|IFFT(c)|^2 and its gradient, 128 orbitals at "
+                       "96^3, complex64 (forward + backward from saved psi)",
+                       {"orbitals": B, "n": n, "precision": "fp32",
+                        "input": "sphere-cutoff orbitals, V = 16 low-|G| cosines"})
+    alg = 16.0 * n ** 3 * B
+    rec.update({
+        "times_ms": {"energy_fwd": round(fwd_ms, 4), "fwd_plus_bwd_saved_psi": round(both_saved, 4),
+                     "fwd_plus_bwd_recompute_psi": round(both_recomp, 4)},
+        "hbm_gbs_algorithmic": round(2 * alg / (both_saved * 1e-3) / 1e9, 1),
+        "rel_l2_vs_fp64": {"E_rel": abs(E.item() - E_all) / abs(E_all),
+                           "grad_first8": float(np.linalg.norm(g8 - g_ref) / np.linalg.norm(g_ref))},
+        "roofline": {"bound": "hbm", "achieved": round(alg / (fwd_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(alg / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "energy_fwd (k_plane_pf + k_axis_str<ENERGY>)",
+                     "ms_per_launch": round(fwd_ms, 5)},
+        "cpu_baseline": None if args.no_cpu_baseline else _cpu_oracle(c, n, 1, args.cpu_seconds, "96^3 orbitals"),
+        "source_hash": source_hash(),
+    })
+    print(json.dumps(rec))
+    return 0
+
+
+def bench_q16(args, prec):
+    """32 x 128^3 in scaled 16-bit storage: inverse then forward, against the
+    FP32 path on the same (dequantized) data."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2006_08435_amd as fft3d
+    from paper_2006_08435_amd import _lib
+    n, B = 128, 32
+    x = make_input(n, B, 3000)
+    xt = torch.from_numpy(x).cuda()
+    qa = fft3d.quantize(xt, prec)
+    qb = torch.empty_like(qa)
+    qc = torch.empty_like(qa)
+    inv = fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_INVERSE)
+    fwd = fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_FORWARD)
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    L = _lib.lib()
+    step = lambda: (inv.exec_ptr(qa.data_ptr(), qb.data_ptr(), sh), fwd.exec_ptr(qb.data_ptr(), qc.data_ptr(), sh))
+    ms = _time(step, args.steps, args.warmup, stream)
+    passes = []
+    for k in range(L.fft3d_plan_passes(inv.handle)):
+        src, dst = (qa, qb) if k == 0 else (qb, qb)
+        t = _time(lambda: _lib.check(L.fft3d_exec_pass(inv.handle, k, src.data_ptr(), dst.data_ptr(), sh)),
+                  max(10, args.steps), 3, stream)
+        passes.append(t)
+    # FP32 reference path on the dequantized input, same step
+    xd = fft3d.dequantize(qa, x.shape, prec)
+    b32, c32 = torch.empty_like(xd), torch.empty_like(xd)
+    inv32 = fft3d.Plan(n, n, n, B, "fp32", fft3d.FFT3D_INVERSE)
+    fwd32 = fft3d.Plan(n, n, n, B, "fp32", fft3d.FFT3D_FORWARD)
+    ms32 = _time(lambda: (inv32.exec_ptr(xd.data_ptr(), b32.data_ptr(), sh),
+                          fwd32.exec_ptr(b32.data_ptr(), c32.data_ptr(), sh)), args.steps, args.warmup, stream)
+    step()
+    torch.cuda.synchronize()
+    fmt = oracle.FMT_FP16 if prec == "fp16" else oracle.FMT_BF16
+    nb = 4 * n ** 3 * B
+    raw = {k: v.cpu().numpy() for k, v in (("a", qa), ("b", qb), ("c", qc))}
+    dec = lambda r, j: oracle.q16_decode(r[:nb].view(np.uint16).reshape(B, n, n, n, 2)[j:j + 1],
+                                          r[nb:].view(np.int8).reshape(B, n, n)[j:j + 1], fmt)
+    e_inv, e_fwd, e_orig = [], [], []
+    for j in (0, 16, 31):
+        xin = dec(raw["a"], j)
+        psi = dec(raw["b"], j)
+        e_inv.append(float(np.linalg.norm(psi - oracle.fft3d(xin, 1)) / np.linalg.norm(oracle.fft3d(xin, 1))))
+        ref_orig = oracle.fft3d(x[j:j + 1].astype(np.complex128), 1)
+        e_orig.append(float(np.linalg.norm(psi - ref_orig) / np.linalg.norm(ref_orig)))
+        back = dec(raw["c"], j)
+        rf = oracle.fft3d(psi, -1)
+        e_fwd.append(float(np.linalg.norm(back - rf) / np.linalg.norm(rf)))
+    flops = 5.0 * n ** 3 * math.log2(n ** 3) * B
+    alg = 8.0 * n ** 3 * B + 2.0 * n * n * B
+    rec = _base_record(2 * flops / (ms * 1e-3) / 1e9, "GFLOP/s", args, ms,
+                       "c2c 3D FFT, 32 grids of 128^3 in scaled %s storage (per-row power-of-two exponent), inverse "
+                       "then forward, radix-16 on MFMA" % prec,
+                       {"n": n, "batch": B, "precision": prec + "_scaled",
+                        "input": "sphere-cutoff plane-wave coefficients, seeds 3000+j, quantized on the GPU"},
+                       dtype="f32 arithmetic, %s storage" % prec)
+    dom = max(range(len(passes)), key=lambda k: passes[k])
+    rec.update({
+        "hbm_gbs_algorithmic": round(2 * alg / (ms * 1e-3) / 1e9, 1),
+        "hbm_frac_algorithmic": round(2 * alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "rel_l2_vs_fp64": {"inverse_vs_dequantized_input_max": max(e_inv), "forward_max": max(e_fwd),
+                           "inverse_vs_original_fp32_input_max": max(e_orig), "grids": [0, 16, 31]},
+        "fp32_same_step_ms": round(ms32, 5), "speedup_vs_fp32": round(ms32 / ms, 3),
+        "kernels_ms_inverse": [round(t, 5) for t in passes],
+        "plans": {"inverse": inv.describe()},
+        "roofline": {"bound": "hbm", "achieved": round(alg / (passes[dom] * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(alg / (passes[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": ["k_q16_plane", "k_q16_slab"][dom] + "<128,1>",
+                     "ms_per_launch": round(passes[dom], 5)},
+        "cpu_baseline": None,
+        "source_hash": source_hash(),
+    })
+    print(json.dumps(rec))
+    return 0
+
+
+def _cpu_oracle(x, n, per, seconds, what):
+    """Oracle (FP64, all host threads) inverse+forward on grids of x until
+    `seconds` have passed."""
+    import numpy as np
+    import oracle
+    threads = oracle.max_threads()
+    done, t0 = 0, time.time()
+    while time.time() - t0 < seconds:
+        y = oracle.fft3d(x[done % len(x)].astype(np.complex128), 1)
+        oracle.fft3d(y, -1)
+        done += 1
+    dt = time.time() - t0
+    return {"value": round(2 * 5.0 * n ** 3 * math.log2(n ** 3) * done / dt / 1e9, 3), "unit": "GFLOP/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "%d %s, inverse then forward, FP64 recursive radix-5/3/2 FFT, %.1f s" % (done, what, dt)}
 
 
 if __name__ == "__main__":

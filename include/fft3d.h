@@ -20,6 +20,18 @@
  * interleaved (re, im) pairs.  FFT3D_FP32 buffers hold complex64 (8 bytes per
  * point).  Output is in natural order, in the same layout as the input.
  *
+ * Scaled 16-bit buffers (FFT3D_FP16_SCALED / FFT3D_BF16_SCALED; the paper's
+ * reduced-precision direction, Section I and the closing paragraph of
+ * Section III): a payload of one 32-bit word per point (low 16 bits the real
+ * part, high 16 bits the imaginary part, as binary16 or bfloat16 patterns),
+ * followed at byte offset 4 * batch * nx*ny*nz by one int8 exponent per
+ * x-row ([batch][z][y], batch*nz*ny bytes).  A point's value is payload *
+ * 2^exponent.  Exponents follow the rule of fft3d_quantize.  These plans need
+ * nx == ny == nz with 16 | n (16, 32, 48, 64, 80, 96, 128); the radix-16
+ * stage runs as a DFT-matrix product with FP16 operands and FP32
+ * accumulation on the matrix cores, everything else in FP32; the
+ * intermediate between the xy and z passes is stored as scaled binary16.
+ *
  * Memory: every data pointer passed to an exec call is a DEVICE pointer
  * (hipMalloc / torch CUDA tensor memory) on the device the plan was created
  * on, aligned to 16 bytes.  The caller owns all buffers and the stream.  A
@@ -128,6 +140,23 @@ int fft3d_plan_passes(fft3d_plan_t plan);
  */
 int fft3d_plan_check(fft3d_plan_t plan);
 int fft3d_exec_pass(fft3d_plan_t plan, int pass, const void *in, void *out, fft3d_stream_t stream);
+
+/*
+ * Conversions between complex64 rows and scaled 16-bit storage, on `stream`.
+ * `rows` rows of `row_len` complex values; in the scaled buffer the payload
+ * (rows*row_len 32-bit words) is followed by `rows` int8 exponents.  Rule per
+ * row: m = max of |re| and |im| over the row; e = 0 if m == 0, otherwise
+ * e = clamp(ilogb(m) - 14, -128, 127); payload = value * 2^-e rounded to
+ * nearest even (so the row maximum is stored in [2^14, 2^15)).
+ * fft3d_dequantize returns the exact values payload * 2^e.  precision is
+ * FFT3D_FP16_SCALED or FFT3D_BF16_SCALED.  Returns FFT3D_OK,
+ * FFT3D_E_INVALID_ARG, FFT3D_E_ALIGNMENT (16-byte device pointers) or
+ * FFT3D_E_LAUNCH.  Inputs must be finite with magnitude below 2^127.
+ */
+int fft3d_quantize(int precision, long rows, int row_len, const void *in_c64, void *out_scaled,
+                   fft3d_stream_t stream);
+int fft3d_dequantize(int precision, long rows, int row_len, const void *in_scaled, void *out_c64,
+                     fft3d_stream_t stream);
 
 /*
  * Heterogeneous batches in one launch.  `count` groups (1 <= count <= 16);

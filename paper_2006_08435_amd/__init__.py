@@ -191,6 +191,42 @@ def _transform(x, direction, out=None):
     return o[0] if squeeze else o
 
 
+def scaled16_bytes(shape) -> int:
+    """Bytes of a scaled 16-bit buffer for complex data of `shape` (last axis = rows)."""
+    n = 1
+    for d in shape:
+        n *= int(d)
+    return 4 * n + n // int(shape[-1])
+
+
+def quantize(x, precision="fp16", out=None, stream=None):
+    """complex64 device tensor -> scaled 16-bit buffer (torch.uint8), rows = last axis."""
+    torch = _torch()
+    if x.dtype != torch.complex64 or not x.is_cuda:
+        raise TypeError("quantize takes a complex64 device tensor")
+    x = x.contiguous()
+    C = int(x.shape[-1])
+    rows = x.numel() // C
+    if out is None:
+        out = torch.empty(scaled16_bytes(x.shape), dtype=torch.uint8, device=x.device)
+    _lib.check(_lib.lib().fft3d_quantize(PRECISIONS[precision], rows, C, x.data_ptr(), out.data_ptr(),
+                                         _stream_handle(stream)), "fft3d_quantize")
+    return out
+
+
+def dequantize(buf, shape, precision="fp16", stream=None):
+    """scaled 16-bit buffer -> complex64 device tensor of `shape` (exact values)."""
+    torch = _torch()
+    C = int(shape[-1])
+    n = 1
+    for d in shape:
+        n *= int(d)
+    out = torch.empty(tuple(int(d) for d in shape), dtype=torch.complex64, device=buf.device)
+    _lib.check(_lib.lib().fft3d_dequantize(PRECISIONS[precision], n // C, C, buf.data_ptr(), out.data_ptr(),
+                                           _stream_handle(stream)), "fft3d_dequantize")
+    return out
+
+
 def fftn(x, out=None):
     """Eq. (1) over the last three axes (sign -1, unnormalised)."""
     return _transform(x, FFT3D_FORWARD, out)
@@ -209,5 +245,5 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-__all__ = ["Plan", "PlanMany", "get_plan", "fftn", "ifftn", "Fft3dError", "FFT3D_FORWARD",
+__all__ = ["Plan", "PlanMany", "get_plan", "quantize", "dequantize", "scaled16_bytes", "fftn", "ifftn", "Fft3dError", "FFT3D_FORWARD",
            "FFT3D_INVERSE", "FFT3D_FP32", "FFT3D_FP16_SCALED", "FFT3D_BF16_SCALED"]

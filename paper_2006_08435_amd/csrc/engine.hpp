@@ -24,9 +24,11 @@
 
 namespace fft3d {
 
-template <int N>
+// KIND 0: default schedule; KIND 1: radix-16 first (make_sched16).
+template <int N, int KIND = 0>
 struct Plan1D {
-    static constexpr Sched sc = make_sched(N);
+    static constexpr int n = N;
+    static constexpr Sched sc = make_sched_kind(N, KIND);
     static constexpr int stages = sc.count;
     static constexpr int radix(int s) { return sc.r[s]; }
     static constexpr int ns(int s) { return sched_ns(sc, s); }
@@ -104,11 +106,11 @@ struct GlobLines {
 // with T threads.  `valid(line)` masks lines beyond a ragged tile end.
 // SYNC: barrier between the read phase and the write phase (needed when
 // source and destination alias in LDS).
-template <int N, int ST, int S, int L, int T, bool LINE_FAST, bool SYNC, class Src, class Dst>
-__device__ __forceinline__ void fft_stage(const Src& src, const Dst& dst, const float2* __restrict__ tw,
+template <class P, int ST, int S, int L, int T, bool LINE_FAST, bool SYNC, class Src, class Dst>
+__device__ __forceinline__ void fft_stage_p(const Src& src, const Dst& dst, const float2* __restrict__ tw,
                                           int tid, int valid_lines = L)
 {
-    using P = Plan1D<N>;
+    constexpr int N = P::n;
     constexpr int R = P::radix(ST);
     constexpr int NS = P::ns(ST);
     constexpr int M = N / R;
@@ -147,6 +149,13 @@ __device__ __forceinline__ void fft_stage(const Src& src, const Dst& dst, const 
             for (int q = 0; q < R; ++q) dst.store(line, base + q * NS, v[it][q]);
         }
     }
+}
+
+template <int N, int ST, int S, int L, int T, bool LINE_FAST, bool SYNC, class Src, class Dst>
+__device__ __forceinline__ void fft_stage(const Src& src, const Dst& dst, const float2* __restrict__ tw, int tid,
+                                          int valid_lines = L)
+{
+    fft_stage_p<Plan1D<N>, ST, S, L, T, LINE_FAST, SYNC>(src, dst, tw, tid, valid_lines);
 }
 
 // All stages of a length-N transform on an LDS tile, in place.

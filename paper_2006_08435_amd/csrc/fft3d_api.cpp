@@ -24,6 +24,7 @@ enum Scheme {
     kPlaneZ = 1,  // xy-plane pass + strided z pass (Nx == Ny)
     kAxes = 2,    // x rows, strided y, strided z
     kFused = 3,   // persistent plane + z-slab kernel (cubic)
+    kQ16 = 4,     // scaled 16-bit storage, radix-16 on the matrix cores (cubic, 16 | N)
 };
 
 int set_error(int code)
@@ -34,9 +35,9 @@ int set_error(int code)
 
 // Angles are reduced to an integer index modulo the root order before
 // cos/sin (double precision), then rounded once to float.
-std::vector<float2> twiddles(int n, int sign)
+std::vector<float2> twiddles(int n, int sign, int kind)
 {
-    const Sched sc = make_sched(n);
+    const Sched sc = make_sched_kind(n, kind);
     std::vector<float2> t(sched_tw_len(sc) > 0 ? sched_tw_len(sc) : 0);
     for (int s = 1; s < sc.count; ++s) {
         const int R = sc.r[s], NS = sched_ns(sc, s), order = NS * R;
@@ -103,7 +104,8 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
     // 2^36 points (512 GiB of complex64) bounds every grid dimension of every
     // launch below 2^31 workgroups.
     if ((long)batch * vol > (1L << 36)) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
-    if (precision != FFT3D_FP32) { set_error(FFT3D_E_UNSUPPORTED); return nullptr; }
+    const bool q16 = precision != FFT3D_FP32;
+    if (q16 && (nx != ny || ny != nz || !q16_plane_fn(nx, direction))) { set_error(FFT3D_E_UNSUPPORTED); return nullptr; }
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -118,7 +120,8 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
     if (!p) { set_error(FFT3D_E_ALLOC); return nullptr; }
     p->nx = nx; p->ny = ny; p->nz = nz; p->batch = batch;
     p->precision = precision; p->direction = direction; p->device = dev; p->vol = vol;
-    if (nx == ny && ny == nz && nx <= kCubeMaxN) p->scheme = kCube;
+    if (q16) p->scheme = kQ16;
+    else if (nx == ny && ny == nz && nx <= kCubeMaxN) p->scheme = kCube;
     else if (nx == ny && ny == nz && fused_fn(nx, direction) && env_flag("FFT3D_FUSED")) p->scheme = kFused;
     else if (nx == ny) p->scheme = kPlaneZ;
     else p->scheme = kAxes;
@@ -126,9 +129,10 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
     // One table per dimension (identical lengths share nothing on purpose:
     // the tables are tiny and separate offsets keep the exec path simple).
     std::vector<float2> tab;
+    const int kind = q16 ? 1 : 0;
     auto append = [&](int n, int sign) {
         const long off = (long)tab.size();
-        std::vector<float2> t = twiddles(n, sign);
+        std::vector<float2> t = twiddles(n, sign, kind);
         tab.insert(tab.end(), t.begin(), t.end());
         // keep every table 16-byte aligned
         if (tab.size() % 2) tab.push_back(make_float2(0.f, 0.f));
@@ -155,7 +159,7 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
         set_error(FFT3D_E_LAUNCH);
         return nullptr;
     }
-    if (nx == ny) {
+    if (nx == ny && !q16) {
         // energy path: persistent plane pass + strided z pass with fused epilogue
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
@@ -173,7 +177,10 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
     const long B = batch;
     const AxisMap zmap{B * ny * nx, nx, ny, vol, (long)nx, (long)nx * ny};
     const AxisMap ymap{B * nz * nx, nx, nz, vol, (long)nx * ny, (long)nx};
-    if (p->scheme == kFused) {
+    if (p->scheme == kQ16) {
+        p->passes.push_back({Pass::kQ16PlaneK, nx, B * nz, {}, p->tw_x, 0});
+        p->passes.push_back({Pass::kQ16SlabK, nx, B * ny, {}, p->tw_x, 0});
+    } else if (p->scheme == kFused) {
         const size_t cb = sizeof(FusedCtl) + sizeof(unsigned) * (size_t)batch;
         if (hipMalloc((void**)&p->ctl, cb) != hipSuccess || hipMemset(p->ctl, 0, cb) != hipSuccess) {
             (void)hipGetLastError();
@@ -236,6 +243,8 @@ size_t fft3d_buffer_bytes(fft3d_plan_t p)
             b += (size_t)p->mp.batch[g] * p->mp.n[g] * p->mp.n[g] * p->mp.n[g] * sizeof(float2);
         return b;
     }
+    if (p->precision != FFT3D_FP32)   // payload (4 B per point) + one exponent byte per x-row
+        return (size_t)p->batch * (size_t)p->vol * 4 + (size_t)p->batch * p->nz * p->ny;
     return (size_t)p->batch * (size_t)p->vol * sizeof(float2);
 }
 
@@ -251,6 +260,16 @@ static hipError_t run_pass(const fft3d_plan_s* p, const Pass& ps, const float2* 
         return plane_pf_fn(ps.n, S)(src, dst, tw, ps.count, ps.grid, 0, nullptr, nullptr, 1, st);
     case Pass::kRowK: return axis_row_fn(ps.n, S)(src, dst, tw, ps.count, st);
     case Pass::kStrK: return axis_str_fn(ps.n, S)(src, dst, tw, ps.map, 0, nullptr, nullptr, 0, st);
+    case Pass::kQ16PlaneK:
+    case Pass::kQ16SlabK: {
+        const size_t pay = (size_t)p->batch * p->vol * 4;
+        const unsigned* ip = reinterpret_cast<const unsigned*>(src);
+        const signed char* ie = reinterpret_cast<const signed char*>(src) + pay;
+        unsigned* op = reinterpret_cast<unsigned*>(dst);
+        signed char* oe = reinterpret_cast<signed char*>(dst) + pay;
+        if (ps.kind == Pass::kQ16PlaneK) return q16_plane_fn(ps.n, S)(ip, ie, op, oe, tw, ps.count, p->precision, st);
+        return q16_slab_fn(ps.n, S)(ip, ie, op, oe, tw, ps.count, p->precision, st);
+    }
     case Pass::kFusedK:
         return fused_fn(ps.n, S)(src, dst, tw, p->ctl, p->batch, p->fused_lag, p->fused_grid, p->fused_chunk, st);
     }
@@ -367,6 +386,36 @@ int fft3d_energy_bwd(fft3d_plan_t p, const void* c_or_psi, int have_psi, const f
     return FFT3D_OK;
 }
 
+int fft3d_quantize(int precision, long rows, int row_len, const void* in, void* out, fft3d_stream_t stream)
+{
+    if ((precision != FFT3D_FP16_SCALED && precision != FFT3D_BF16_SCALED) || rows < 0 || row_len < 1 || !in || !out)
+        return FFT3D_E_INVALID_ARG;
+    if (((uintptr_t)in % 16) || ((uintptr_t)out % 16)) return FFT3D_E_ALIGNMENT;
+    unsigned* pay = static_cast<unsigned*>(out);
+    signed char* ex = reinterpret_cast<signed char*>(pay + (size_t)rows * row_len);
+    if (launch_quantize(precision, static_cast<const float2*>(in), rows, row_len, pay, ex,
+                        reinterpret_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
+int fft3d_dequantize(int precision, long rows, int row_len, const void* in, void* out, fft3d_stream_t stream)
+{
+    if ((precision != FFT3D_FP16_SCALED && precision != FFT3D_BF16_SCALED) || rows < 0 || row_len < 1 || !in || !out)
+        return FFT3D_E_INVALID_ARG;
+    if (((uintptr_t)in % 16) || ((uintptr_t)out % 16)) return FFT3D_E_ALIGNMENT;
+    const unsigned* pay = static_cast<const unsigned*>(in);
+    const signed char* ex = reinterpret_cast<const signed char*>(pay + (size_t)rows * row_len);
+    if (launch_dequantize(precision, pay, ex, rows, row_len, static_cast<float2*>(out),
+                          reinterpret_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
 int fft3d_plan_check(fft3d_plan_t p)
 {
     if (!p) return FFT3D_E_INVALID_ARG;
@@ -399,7 +448,16 @@ int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
     };
     std::string d;
     char tmp[256];
-    if (p->scheme == kFused) {
+    if (p->scheme == kQ16) {
+        const KernelInfo k = q16_info(p->nx);
+        const Sched sc = make_sched16(p->nx);
+        std::string r;
+        for (int i = 0; i < sc.count; ++i) r += (i ? "x" : "") + std::to_string(sc.r[i]);
+        snprintf(tmp, sizeof tmp, "scaled16 %s n=%d radices=%s(radix-16 on MFMA) threads=%d lds=%d planes=%ld",
+                 p->precision == FFT3D_FP16_SCALED ? "fp16" : "bf16", p->nx, r.c_str(), k.threads, k.lds_bytes,
+                 (long)p->batch * p->nz);
+        d = tmp;
+    } else if (p->scheme == kFused) {
         const KernelInfo k = fused_info(p->nx);
         snprintf(tmp, sizeof tmp, "fused n=%d radices=%s threads=%d lds=%d grids=%d workgroups=%d lag=%d", p->nx,
                  radices(p->nx).c_str(), k.threads, k.lds_bytes, p->batch, p->fused_grid, p->fused_lag);
@@ -424,7 +482,8 @@ int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
     d += p->direction < 0 ? " forward" : " inverse";
     d += " kernels=";
     for (size_t i = 0; i < p->passes.size(); ++i) {
-        static const char* names[] = {"k_cube", "k_plane", "k_plane_pf", "k_axis_row", "k_axis_str", "k_fused"};
+        static const char* names[] = {"k_cube", "k_plane", "k_plane_pf", "k_axis_row", "k_axis_str", "k_fused",
+                                      "k_q16_plane", "k_q16_slab"};
         d += (i ? "," : "") + std::string(names[p->passes[i].kind]);
     }
     if (buf && len) {

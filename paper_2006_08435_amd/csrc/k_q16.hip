@@ -1,0 +1,93 @@
+// Reduced-precision (scaled16) kernel instances and launchers.
+#include "kernels_q16.hpp"
+#include "registry.hpp"
+
+namespace fft3d {
+
+template <int N, int S>
+static hipError_t launch_plane(const unsigned* ip, const signed char* ie, unsigned* mp, signed char* me,
+                               const float2* tw, long planes, int fmt_in, hipStream_t st)
+{
+    if (fmt_in == kFmtF16)
+        hipLaunchKernelGGL((k_q16_plane<N, S, kFmtF16>), dim3((unsigned)planes), dim3(Q16Geom<N>::T), 0, st, ip, ie,
+                           mp, me, tw);
+    else
+        hipLaunchKernelGGL((k_q16_plane<N, S, kFmtBF16>), dim3((unsigned)planes), dim3(Q16Geom<N>::T), 0, st, ip,
+                           ie, mp, me, tw);
+    return hipGetLastError();
+}
+
+template <int N, int S>
+static hipError_t launch_slab(const unsigned* mp, const signed char* me, unsigned* op, signed char* oe,
+                              const float2* tw, long slabs, int fmt_out, hipStream_t st)
+{
+    if (fmt_out == kFmtF16)
+        hipLaunchKernelGGL((k_q16_slab<N, S, kFmtF16>), dim3((unsigned)slabs), dim3(Q16Geom<N>::T), 0, st, mp, me, op,
+                           oe, tw);
+    else
+        hipLaunchKernelGGL((k_q16_slab<N, S, kFmtBF16>), dim3((unsigned)slabs), dim3(Q16Geom<N>::T), 0, st, mp, me,
+                           op, oe, tw);
+    return hipGetLastError();
+}
+
+#define FFT3D_Q16_SIZES(X) X(16) X(32) X(48) X(64) X(80) X(96) X(128)
+
+Q16PlaneFn q16_plane_fn(int n, int sign)
+{
+    switch (n) {
+#define C(m) \
+    case m: return sign < 0 ? &launch_plane<m, -1> : &launch_plane<m, 1>;
+        FFT3D_Q16_SIZES(C)
+#undef C
+    default: return nullptr;
+    }
+}
+
+Q16SlabFn q16_slab_fn(int n, int sign)
+{
+    switch (n) {
+#define C(m) \
+    case m: return sign < 0 ? &launch_slab<m, -1> : &launch_slab<m, 1>;
+        FFT3D_Q16_SIZES(C)
+#undef C
+    default: return nullptr;
+    }
+}
+
+KernelInfo q16_info(int n)
+{
+    switch (n) {
+#define C(m) \
+    case m: return {Q16Geom<m>::T, (int)(Q16Geom<m>::WORDS * sizeof(float2) + m * sizeof(int))};
+        FFT3D_Q16_SIZES(C)
+#undef C
+    default: return {0, 0};
+    }
+}
+
+hipError_t launch_quantize(int fmt, const float2* in, long rows, int C, unsigned* pay, signed char* ex,
+                           hipStream_t st)
+{
+    const long blocks = (rows + 3) / 4;
+    if (blocks == 0) return hipSuccess;
+    if (fmt == kFmtF16)
+        hipLaunchKernelGGL(k_q16_quantize<kFmtF16>, dim3((unsigned)blocks), dim3(256), 0, st, in, rows, C, pay, ex);
+    else
+        hipLaunchKernelGGL(k_q16_quantize<kFmtBF16>, dim3((unsigned)blocks), dim3(256), 0, st, in, rows, C, pay, ex);
+    return hipGetLastError();
+}
+
+hipError_t launch_dequantize(int fmt, const unsigned* pay, const signed char* ex, long rows, int C, float2* out,
+                             hipStream_t st)
+{
+    const long blocks = (rows * C + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    if (fmt == kFmtF16)
+        hipLaunchKernelGGL(k_q16_dequantize<kFmtF16>, dim3((unsigned)blocks), dim3(256), 0, st, pay, ex, rows, C, out);
+    else
+        hipLaunchKernelGGL(k_q16_dequantize<kFmtBF16>, dim3((unsigned)blocks), dim3(256), 0, st, pay, ex, rows, C,
+                           out);
+    return hipGetLastError();
+}
+
+}  // namespace fft3d

@@ -34,6 +34,13 @@ constexpr int threads_for(int lines)
     return t < 64 ? 64 : (t > 1024 ? 1024 : t);
 }
 
+template <int N, int KIND>
+constexpr int threads_for_kind(int lines)
+{
+    int t = round_up(lines * N / Plan1D<N, KIND>::max_radix, 64);
+    return t < 64 ? 64 : (t > 1024 ? 1024 : t);
+}
+
 // 2D LDS accessor: line -> (hi, lo) = (line / LDIV, line % LDIV);
 // address = hi * LHI + lo * LLO + e * ES.
 template <int LDIV, int LHI, int LLO, int ES>

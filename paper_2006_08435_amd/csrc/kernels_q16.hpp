@@ -1,0 +1,288 @@
+// Reduced-precision form: scaled 16-bit storage with FP32 arithmetic and the
+// radix-16 stage as a DFT-matrix product on the matrix cores.
+//
+// Storage ("scaled16"): a buffer of R rows of C complex values holds a
+// payload of R*C 32-bit words (low half = real part, high half = imaginary
+// part, each a binary16 or bfloat16 pattern) followed by R int8 exponents;
+// the value of an entry is payload * 2^exponent.  Exponent rule per row:
+// m = max |re|, |im| over the row; e = 0 if m == 0, else
+// clamp(ilogb(m) - 14, -128, 127), so the scaled row maximum lies in
+// [2^14, 2^15).  Conversions round to nearest, ties to even.
+//
+// Transform (cubic N, 16 | N): the 1D schedule is radix 16 first, then the
+// default schedule of N / 16.  The radix-16 stage multiplies 16-point columns
+// by the DFT matrix written as a real 32x32 matrix [[C, -sS], [sS, C]]
+// (C = cos, S = sin of 2 pi m k / 16, s = exponent sign) with
+// v_mfma_f32_16x16x32_f16: FP16 operands (each column scaled by a power of
+// two so its largest component lies in [2^14, 2^15)), FP32 accumulation.
+// Twiddles and the other radices run in FP32 on the vector ALUs.  Pass A
+// (xy-planes) stores its intermediate as scaled FP16 whatever the output
+// format; pass B (xz-slabs) stores the result in the plan's format.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels_fp32.hpp"
+
+namespace fft3d {
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kFmtF16 = 1;
+constexpr int kFmtBF16 = 2;
+
+template <int FMT>
+__device__ __forceinline__ float dec16(unsigned h)
+{
+    if constexpr (FMT == kFmtF16) return (float)__builtin_bit_cast(_Float16, (unsigned short)h);
+    else return __builtin_bit_cast(float, h << 16);
+}
+
+// Round to nearest even into the 16-bit pattern.
+template <int FMT>
+__device__ __forceinline__ unsigned enc16(float x)
+{
+    if constexpr (FMT == kFmtF16) {
+        return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)x);
+    } else {
+        const unsigned u = __builtin_bit_cast(unsigned, x);
+        return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    }
+}
+
+// Row exponent of the storage rule for a row maximum m >= 0.
+__device__ __forceinline__ int row_exponent(float m)
+{
+    if (m == 0.f) return 0;
+    int e = __builtin_amdgcn_frexp_expf(m) - 1 - 14;   // ilogb(m) - 14
+    return e < -128 ? -128 : (e > 127 ? 127 : e);
+}
+
+template <int N>
+struct Q16Geom {
+    static constexpr int RS = odd_stride(N);
+    static constexpr int WORDS = N * RS;
+    static constexpr int T = threads_for_kind<N, 1>(N);
+};
+
+// Load NR rows of N scaled16 values (row r's payload at pay + r * rstride,
+// its exponent at ex[r * estride]) and store their exact FP32 values into
+// the LDS tile (row stride RS).  All global loads are issued first.
+template <int NR, int N, int RS, int T, int FMT>
+__device__ __forceinline__ void q16_load_tile(const unsigned* pay, long rstride, const signed char* ex, long estride,
+                                              float2* lds, int* lds_e, int tid)
+{
+    static_assert(N % 4 == 0, "rows move as 16-byte units");
+    constexpr int UNITS = NR * N / 4, IT = (UNITS + T - 1) / T;
+    uint4 u[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const int i = tid + k * T;
+        if (UNITS % T == 0 || i < UNITS) {
+            const int r = (4 * i) / N, x = (4 * i) % N;
+            u[k] = *reinterpret_cast<const uint4*>(pay + r * rstride + x);
+        }
+    }
+    for (int r = tid; r < NR; r += T) lds_e[r] = ex[r * estride];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const int i = tid + k * T;
+        if (UNITS % T == 0 || i < UNITS) {
+            const int r = (4 * i) / N, x = (4 * i) % N;
+            const int e = lds_e[r];
+            float2* d = lds + r * RS + x;
+            d[0] = make_float2(ldexpf(dec16<FMT>(u[k].x & 0xFFFFu), e), ldexpf(dec16<FMT>(u[k].x >> 16), e));
+            d[1] = make_float2(ldexpf(dec16<FMT>(u[k].y & 0xFFFFu), e), ldexpf(dec16<FMT>(u[k].y >> 16), e));
+            d[2] = make_float2(ldexpf(dec16<FMT>(u[k].z & 0xFFFFu), e), ldexpf(dec16<FMT>(u[k].z >> 16), e));
+            d[3] = make_float2(ldexpf(dec16<FMT>(u[k].w & 0xFFFFu), e), ldexpf(dec16<FMT>(u[k].w >> 16), e));
+        }
+    }
+}
+
+// Requantize NR rows of N FP32 values from the LDS tile to scaled16: one
+// wave per row (lanes along the row), row maximum by a wave reduction.
+template <int NR, int N, int RS, int T, int FMT>
+__device__ __forceinline__ void q16_store_rows(const float2* lds, unsigned* pay, long rstride, signed char* ex,
+                                               long estride, int tid)
+{
+    constexpr int W = T / 64, PER = (N + 63) / 64;
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int r = wave; r < NR; r += W) {
+        float2 v[PER];
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int x = lane + 64 * k;
+            v[k] = x < N ? lds[r * RS + x] : make_float2(0.f, 0.f);
+            m = fmaxf(m, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        const int e = row_exponent(m);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int x = lane + 64 * k;
+            if (x < N)
+                pay[r * rstride + x] = enc16<FMT>(ldexpf(v[k].x, -e)) | (enc16<FMT>(ldexpf(v[k].y, -e)) << 16);
+        }
+        if (lane == 0) ex[r * estride] = (signed char)e;
+    }
+}
+
+// cos and sin of 2 pi t / 16, t = 0..15.
+__device__ __forceinline__ float cos16(int t)
+{
+    constexpr float c[16] = {1.0f, 0.92387953251128676f, 0.70710678118654752f, 0.38268343236508977f, 0.0f,
+                             -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128676f, -1.0f,
+                             -0.92387953251128676f, -0.70710678118654752f, -0.38268343236508977f, 0.0f,
+                             0.38268343236508977f, 0.70710678118654752f, 0.92387953251128676f};
+    return c[t & 15];
+}
+__device__ __forceinline__ float sin16(int t) { return cos16(t + 12); }   // sin x = cos(x - pi/2)
+
+// Radix-16 stage 0 of schedule KIND 1 on an LDS tile (L lines of N, line
+// stride LS, element stride ES), in place, on the matrix cores.  A wave takes
+// 16 columns (line, j) at a time: lane l holds 8 real or 8 imaginary parts
+// of column l % 16 (operand row block 8 * (l / 16)); two 16x16x32 products
+// give the real and imaginary outputs, 4 per lane (rows 4 * (l / 16) + i).
+template <int N, int S, int L, int T, int LS, int ES>
+__device__ __forceinline__ void mfma_stage16(float2* lds, int tid)
+{
+    constexpr int M = N / 16, COLS = L * M, GROUPS = COLS / 16, W = T / 64, GPW = (GROUPS + W - 1) / W;
+    static_assert(COLS % 16 == 0, "columns come in groups of 16");
+    const int lane = tid & 63, wave = tid >> 6, c16 = lane & 15, h = lane >> 4;
+    half8_t are, aim;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int kk = 8 * h + i, k = kk & 15, t = (c16 * k) & 15;
+        const float c = cos16(t), sn = (S > 0 ? 1.f : -1.f) * sin16(t);
+        are[i] = (_Float16)(kk < 16 ? c : -sn);
+        aim[i] = (_Float16)(kk < 16 ? sn : c);
+    }
+    float2 outv[GPW][4];
+#pragma unroll
+    for (int g = 0; g < GPW; ++g) {
+        const int G = wave + g * W;
+        if (GROUPS % W == 0 || G < GROUPS) {
+            const int col = G * 16 + c16, line = col % L, j = col / L;
+            const float* f = reinterpret_cast<const float*>(lds + line * LS + j * ES) + (h >> 1);
+            float v[8], mx = 0.f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int p = 8 * (h & 1) + i;
+                v[i] = f[2 * p * M * ES];
+                mx = fmaxf(mx, fabsf(v[i]));
+            }
+            mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+            mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+            const int e2 = mx > 0.f ? __builtin_amdgcn_frexp_expf(mx) : 0;   // mx in [2^(e2-1), 2^e2)
+            half8_t b;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) b[i] = (_Float16)ldexpf(v[i], 15 - e2);
+            const f32x4_t z = {0.f, 0.f, 0.f, 0.f};
+            const f32x4_t dre = __builtin_amdgcn_mfma_f32_16x16x32_f16(are, b, z, 0, 0, 0);
+            const f32x4_t dim = __builtin_amdgcn_mfma_f32_16x16x32_f16(aim, b, z, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) outv[g][i] = make_float2(ldexpf(dre[i], e2 - 15), ldexpf(dim[i], e2 - 15));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < GPW; ++g) {
+        const int G = wave + g * W;
+        if (GROUPS % W == 0 || G < GROUPS) {
+            const int col = G * 16 + c16, line = col % L, j = col / L;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) lds[line * LS + (j * 16 + 4 * h + i) * ES] = outv[g][i];
+        }
+    }
+}
+
+// All stages of a length-N KIND-1 transform on an LDS tile, in place; ends
+// with a barrier.
+template <int N, int S, int L, int T, int LS, int ES>
+__device__ __forceinline__ void q16_fft_lds(float2* lds, const float2* __restrict__ tw, int tid)
+{
+    using P = Plan1D<N, 1>;
+    mfma_stage16<N, S, L, T, LS, ES>(lds, tid);
+    __syncthreads();
+    const LdsAcc<LS, ES> a{lds};
+    if constexpr (P::stages > 1) { fft_stage_p<P, 1, S, L, T, true, true>(a, a, tw, tid); __syncthreads(); }
+    if constexpr (P::stages > 2) { fft_stage_p<P, 2, S, L, T, true, true>(a, a, tw, tid); __syncthreads(); }
+    if constexpr (P::stages > 3) { fft_stage_p<P, 3, S, L, T, true, true>(a, a, tw, tid); __syncthreads(); }
+    if constexpr (P::stages > 4) { fft_stage_p<P, 4, S, L, T, true, true>(a, a, tw, tid); __syncthreads(); }
+}
+
+// Pass A: plane p = b * N + z.  Rows of the input (b, z, y) -> rows of the
+// FP16 intermediate (b, z, ky).
+template <int N, int S, int FMT_IN>
+__global__ void __launch_bounds__(Q16Geom<N>::T)
+k_q16_plane(const unsigned* in_pay, const signed char* in_exp, unsigned* mid_pay, signed char* mid_exp,
+            const float2* __restrict__ tw)
+{
+    using G = Q16Geom<N>;
+    constexpr int T = G::T, RS = G::RS;
+    __shared__ float2 lds[G::WORDS];
+    __shared__ int lds_e[N];
+    const int tid = threadIdx.x;
+    const long p = blockIdx.x;
+    q16_load_tile<N, N, RS, T, FMT_IN>(in_pay + p * N * N, N, in_exp + p * N, 1, lds, lds_e, tid);
+    __syncthreads();
+    q16_fft_lds<N, S, N, T, RS, 1>(lds, tw, tid);   // x: lines = rows
+    q16_fft_lds<N, S, N, T, 1, RS>(lds, tw, tid);   // y: lines = columns
+    q16_store_rows<N, N, RS, T, kFmtF16>(lds, mid_pay + p * N * N, N, mid_exp + p * N, 1, tid);
+}
+
+// Pass B: slab s = b * N + y; rows (b, z, y) of the intermediate for all z
+// -> rows (b, kz, y) of the output.
+template <int N, int S, int FMT_OUT>
+__global__ void __launch_bounds__(Q16Geom<N>::T)
+k_q16_slab(const unsigned* mid_pay, const signed char* mid_exp, unsigned* out_pay, signed char* out_exp,
+           const float2* __restrict__ tw)
+{
+    using G = Q16Geom<N>;
+    constexpr int T = G::T, RS = G::RS;
+    __shared__ float2 lds[G::WORDS];
+    __shared__ int lds_e[N];
+    const int tid = threadIdx.x;
+    const long s = blockIdx.x, b = s / N, y = s % N;
+    const long row0 = b * N * N + y;   // row index of (b, z = 0, y); rows of successive z are N apart
+    q16_load_tile<N, N, RS, T, kFmtF16>(mid_pay + row0 * N, (long)N * N, mid_exp + row0, N, lds, lds_e, tid);
+    __syncthreads();
+    q16_fft_lds<N, S, N, T, 1, RS>(lds, tw, tid);   // z: lines = x, elements along z (LDS rows)
+    q16_store_rows<N, N, RS, T, FMT_OUT>(lds, out_pay + row0 * N, (long)N * N, out_exp + row0, N, tid);
+}
+
+// Standalone conversions (fft3d_quantize / fft3d_dequantize): one wave per
+// row of C values; rows of FP32 complex in, scaled16 out, and back.
+template <int FMT>
+__global__ void __launch_bounds__(256) k_q16_quantize(const float2* in, long rows, int C, unsigned* pay,
+                                                      signed char* ex)
+{
+    const int lane = threadIdx.x & 63;
+    const long r = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows) return;
+    const float2* row = in + r * C;
+    float m = 0.f;
+    for (int x = lane; x < C; x += 64) m = fmaxf(m, fmaxf(fabsf(row[x].x), fabsf(row[x].y)));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    const int e = row_exponent(m);
+    for (int x = lane; x < C; x += 64)
+        pay[r * C + x] = enc16<FMT>(ldexpf(row[x].x, -e)) | (enc16<FMT>(ldexpf(row[x].y, -e)) << 16);
+    if (lane == 0) ex[r] = (signed char)e;
+}
+
+template <int FMT>
+__global__ void __launch_bounds__(256) k_q16_dequantize(const unsigned* pay, const signed char* ex, long rows, int C,
+                                                        float2* out)
+{
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= rows * C) return;
+    const int e = ex[i / C];
+    const unsigned u = pay[i];
+    out[i] = make_float2(ldexpf(dec16<FMT>(u & 0xFFFFu), e), ldexpf(dec16<FMT>(u >> 16), e));
+}
+
+}  // namespace fft3d

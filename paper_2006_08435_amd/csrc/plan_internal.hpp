@@ -18,12 +18,12 @@ int last_error_value();
 void clear_error();
 bool env_flag(const char* name);
 // Twiddle table of a length-n transform for exponent sign `sign` (sched.hpp layout).
-std::vector<float2> twiddles(int n, int sign);
+std::vector<float2> twiddles(int n, int sign, int kind = 0);
 
 // One kernel launch of an exec.  The first pass reads the caller's input,
 // every later pass works in place on the output buffer.
 struct Pass {
-    enum Kind { kCubeK, kPlaneK, kPlanePfK, kRowK, kStrK, kFusedK } kind;
+    enum Kind { kCubeK, kPlaneK, kPlanePfK, kRowK, kStrK, kFusedK, kQ16PlaneK, kQ16SlabK } kind;
     int n;        // transform length of this pass
     long count;   // grids / planes / rows (cube, plane, row kinds)
     AxisMap map;  // strided kind

@@ -48,6 +48,18 @@ bool many_size_ok(int n);
 size_t many_lds_bytes(int n, int threads);   // dynamic LDS one size-n item needs
 int many_per_item(int n, int threads);       // planes (slabs) per work item
 
+// Reduced-precision (scaled16) passes; fmt 1 = binary16, 2 = bfloat16.
+using Q16PlaneFn = hipError_t (*)(const unsigned* in_pay, const signed char* in_exp, unsigned* mid_pay,
+                                  signed char* mid_exp, const float2* tw, long planes, int fmt_in, hipStream_t st);
+using Q16SlabFn = hipError_t (*)(const unsigned* mid_pay, const signed char* mid_exp, unsigned* out_pay,
+                                 signed char* out_exp, const float2* tw, long slabs, int fmt_out, hipStream_t st);
+Q16PlaneFn q16_plane_fn(int n, int sign);
+Q16SlabFn q16_slab_fn(int n, int sign);
+hipError_t launch_quantize(int fmt, const float2* in, long rows, int C, unsigned* pay, signed char* ex,
+                           hipStream_t st);
+hipError_t launch_dequantize(int fmt, const unsigned* pay, const signed char* ex, long rows, int C, float2* out,
+                             hipStream_t st);
+
 // Kernel geometry (threads, LDS bytes) for diagnostics.
 struct KernelInfo {
     int threads;
@@ -58,5 +70,6 @@ KernelInfo plane_info(int n);
 KernelInfo axis_str_info(int n);
 KernelInfo axis_row_info(int n);
 KernelInfo fused_info(int n);
+KernelInfo q16_info(int n);
 
 }  // namespace fft3d

@@ -44,6 +44,25 @@ __host__ __device__ constexpr Sched make_sched(int n)
     return s;
 }
 
+// Schedule of the reduced-precision form: a radix-16 first stage (computed
+// as a DFT-matrix product on the matrix cores) followed by the default
+// schedule of N / 16.  Requires 16 | N.
+__host__ __device__ constexpr Sched make_sched16(int n)
+{
+    Sched s{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+    s.r[s.count++] = 16;
+    if (n / 16 > 1) {
+        const Sched t = make_sched(n / 16);
+        for (int i = 0; i < t.count; ++i) s.r[s.count++] = t.r[i];
+    }
+    return s;
+}
+
+__host__ __device__ constexpr Sched make_sched_kind(int n, int kind)
+{
+    return kind == 1 ? make_sched16(n) : make_sched(n);
+}
+
 __host__ __device__ constexpr int sched_ns(const Sched& s, int stage)
 {
     int p = 1;

@@ -1,0 +1,140 @@
+"""Reduced-precision form: scaled 16-bit storage (binary16 / bfloat16 payload,
+per-row power-of-two exponent), FP32 arithmetic, radix-16 on the matrix
+cores.  Bars: conversions bit-exact against the oracle's encoder; transforms
+within relative L2 2e-3 of the FP64 oracle applied to the dequantized input."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL16 = 2e-3
+FMT = {"fp16": oracle.FMT_FP16, "bf16": oracle.FMT_BF16}
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128).ravel()
+    b = np.asarray(b, np.complex128).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_2006_08435_amd as m
+    return m
+
+
+def split(buf, shape):
+    """scaled16 byte buffer -> (uint16 payload [..., 2], int8 exps) numpy views."""
+    n = int(np.prod(shape))
+    b = buf.cpu().numpy()
+    pay = b[:4 * n].view(np.uint16).reshape(tuple(shape) + (2,))
+    ex = b[4 * n:].view(np.int8).reshape(tuple(shape[:-1]))
+    return pay, ex
+
+
+def join(pay, ex):
+    return torch.from_numpy(np.concatenate([pay.reshape(-1).view(np.uint8), ex.reshape(-1).view(np.uint8)])).cuda()
+
+
+def rows_fixture():
+    rng = np.random.default_rng(17)
+    a = (rng.standard_normal((96, 40)) + 1j * rng.standard_normal((96, 40)))
+    a *= 2.0 ** rng.integers(-40, 40, (96, 1))
+    a[2] = 0
+    a[3] = 0
+    a[3, 5] = 2.0 ** 14
+    a[4] = 0
+    a[4, 0] = -1j * 2.0 ** 15
+    a[5] *= 1e-30
+    a[6, ::2] *= 1e-6       # wide dynamic range inside one row
+    return a.astype(np.complex64)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_quantize_bit_exact(F, prec):
+    a = rows_fixture()
+    buf = F.quantize(torch.from_numpy(a).cuda(), prec)
+    torch.cuda.synchronize()
+    pay, ex = split(buf, a.shape)
+    rp, re_ = oracle.q16_encode(a, FMT[prec])
+    assert np.array_equal(ex, re_)
+    assert np.array_equal(pay, rp)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_dequantize_bit_exact(F, prec):
+    a = rows_fixture()
+    rp, re_ = oracle.q16_encode(a, FMT[prec])
+    got = F.dequantize(join(rp, re_), a.shape, prec).cpu().numpy()
+    want = oracle.q16_decode(rp, re_, FMT[prec])
+    assert np.array_equal(got.astype(np.complex128), want)
+
+
+def run_q16(F, x, prec, direction, inplace=False):
+    b, n = x.shape[0], x.shape[-1]
+    xt = torch.from_numpy(x).cuda()
+    qin = F.quantize(xt, prec)
+    plan = F.Plan(n, n, n, b, prec, direction)
+    if inplace:
+        plan.exec(qin, qin)
+        out = qin
+    else:
+        out = plan.exec(qin)
+    torch.cuda.synchronize()
+    pin, ein = split(qin if not inplace else F.quantize(xt, prec), x.shape)
+    pout, eout = split(out, x.shape)
+    return plan, pin, ein, pout, eout
+
+
+@pytest.mark.parametrize("n", [16, 32, 48, 64, 80, 96, 128])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("direction", [1, -1])
+def test_transform_within_bound(F, n, prec, direction):
+    b = 2 if n <= 64 else 1
+    x = np.stack([workloads.sphere_grid(n, 900 + n + j) for j in range(b)])
+    plan, pin, ein, pout, eout = run_q16(F, x, prec, direction)
+    assert "scaled16" in plan.describe() and "MFMA" in plan.describe()
+    xin = oracle.q16_decode(pin, ein, FMT[prec])        # the input IS the 16-bit data
+    got = oracle.q16_decode(pout, eout, FMT[prec])
+    ref = oracle.fft3d(xin, direction)
+    for j in range(b):
+        r = rel(got[j], ref[j])
+        assert r <= TOL16, (n, prec, direction, j, r)
+
+
+def test_inplace_matches_out_of_place(F):
+    x = np.stack([workloads.sphere_grid(64, 5 + j) for j in range(3)])
+    _, _, _, p1, e1 = run_q16(F, x, "fp16", 1)
+    _, _, _, p2, e2 = run_q16(F, x, "fp16", 1, inplace=True)
+    assert np.array_equal(p1, p2) and np.array_equal(e1, e2)
+
+
+def test_matches_fp32_path(F):
+    """The 16-bit transform equals the FP32 transform of the same (dequantized)
+    input to the same bound."""
+    n = 96
+    x = workloads.sphere_grid(n, 77)[None]
+    _, pin, ein, pout, eout = run_q16(F, x, "fp16", -1)
+    xin = oracle.q16_decode(pin, ein, oracle.FMT_FP16).astype(np.complex64)
+    y32 = F.fftn(torch.from_numpy(xin).cuda()).cpu().numpy()
+    assert rel(oracle.q16_decode(pout, eout, oracle.FMT_FP16), y32) <= TOL16
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_batch_32x128(F, prec):
+    """32 grids of 128^3 (the large precision-form workload)."""
+    B, n = 32, 128
+    x = np.empty((B, n, n, n), np.complex64)
+    for j in range(B):
+        x[j] = workloads.sphere_grid(n, workloads.SEED_BATCH128 + j)
+    for direction in (1, -1):
+        _, pin, ein, pout, eout = run_q16(F, x, prec, direction)
+        for j in (0, 17, 31):
+            xin = oracle.q16_decode(pin[j:j + 1], ein[j:j + 1], FMT[prec])
+            got = oracle.q16_decode(pout[j:j + 1], eout[j:j + 1], FMT[prec])
+            r = rel(got, oracle.fft3d(xin, direction))
+            assert r <= TOL16, (prec, direction, j, r)
