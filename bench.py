@@ -37,10 +37,11 @@ EXTRA_WORKLOADS = ("mixed", "energy96", "fp16_128", "bf16_128")
 
 
 def source_hash() -> str:
+    """Hash of the device-code sources (kernels and their launchers)."""
     h = hashlib.sha1()
     csrc = os.path.join(ROOT, "paper_2006_08435_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".cpp")):
+        if f.endswith((".hip", ".hpp")):
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
@@ -410,6 +411,13 @@ def bench_q16(args, prec):
         t = _time(lambda: _lib.check(L.fft3d_exec_pass(inv.handle, k, src.data_ptr(), dst.data_ptr(), sh)),
                   max(10, args.steps), 3, stream)
         passes.append(t)
+    # the same step with the radix-16 stage on the vector ALUs (FFT3D_Q16_VALU=1 at plan time)
+    os.environ["FFT3D_Q16_VALU"] = "1"
+    inv_v = fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_INVERSE)
+    fwd_v = fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_FORWARD)
+    del os.environ["FFT3D_Q16_VALU"]
+    ms_valu = _time(lambda: (inv_v.exec_ptr(qa.data_ptr(), qb.data_ptr(), sh),
+                             fwd_v.exec_ptr(qb.data_ptr(), qc.data_ptr(), sh)), args.steps, args.warmup, stream)
     # FP32 reference path on the dequantized input, same step
     xd = fft3d.dequantize(qa, x.shape, prec)
     b32, c32 = torch.empty_like(xd), torch.empty_like(xd)
@@ -449,6 +457,7 @@ def bench_q16(args, prec):
         "rel_l2_vs_fp64": {"inverse_vs_dequantized_input_max": max(e_inv), "forward_max": max(e_fwd),
                            "inverse_vs_original_fp32_input_max": max(e_orig), "grids": [0, 16, 31]},
         "fp32_same_step_ms": round(ms32, 5), "speedup_vs_fp32": round(ms32 / ms, 3),
+        "radix16_engine_ms": {"mfma": round(ms, 5), "valu": round(ms_valu, 5)},
         "kernels_ms_inverse": [round(t, 5) for t in passes],
         "plans": {"inverse": inv.describe()},
         "roofline": {"bound": "hbm", "achieved": round(alg / (passes[dom] * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,

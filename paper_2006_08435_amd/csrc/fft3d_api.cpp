@@ -120,7 +120,10 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
     if (!p) { set_error(FFT3D_E_ALLOC); return nullptr; }
     p->nx = nx; p->ny = ny; p->nz = nz; p->batch = batch;
     p->precision = precision; p->direction = direction; p->device = dev; p->vol = vol;
-    if (q16) p->scheme = kQ16;
+    if (q16) {
+        p->scheme = kQ16;
+        p->q16_valu = env_flag("FFT3D_Q16_VALU");
+    }
     else if (nx == ny && ny == nz && nx <= kCubeMaxN) p->scheme = kCube;
     else if (nx == ny && ny == nz && fused_fn(nx, direction) && env_flag("FFT3D_FUSED")) p->scheme = kFused;
     else if (nx == ny) p->scheme = kPlaneZ;
@@ -267,8 +270,9 @@ static hipError_t run_pass(const fft3d_plan_s* p, const Pass& ps, const float2* 
         const signed char* ie = reinterpret_cast<const signed char*>(src) + pay;
         unsigned* op = reinterpret_cast<unsigned*>(dst);
         signed char* oe = reinterpret_cast<signed char*>(dst) + pay;
-        if (ps.kind == Pass::kQ16PlaneK) return q16_plane_fn(ps.n, S)(ip, ie, op, oe, tw, ps.count, p->precision, st);
-        return q16_slab_fn(ps.n, S)(ip, ie, op, oe, tw, ps.count, p->precision, st);
+        const int f = p->precision | (p->q16_valu ? 16 : 0);
+        if (ps.kind == Pass::kQ16PlaneK) return q16_plane_fn(ps.n, S)(ip, ie, op, oe, tw, ps.count, f, st);
+        return q16_slab_fn(ps.n, S)(ip, ie, op, oe, tw, ps.count, f, st);
     }
     case Pass::kFusedK:
         return fused_fn(ps.n, S)(src, dst, tw, p->ctl, p->batch, p->fused_lag, p->fused_grid, p->fused_chunk, st);
@@ -453,8 +457,9 @@ int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
         const Sched sc = make_sched16(p->nx);
         std::string r;
         for (int i = 0; i < sc.count; ++i) r += (i ? "x" : "") + std::to_string(sc.r[i]);
-        snprintf(tmp, sizeof tmp, "scaled16 %s n=%d radices=%s(radix-16 on MFMA) threads=%d lds=%d planes=%ld",
-                 p->precision == FFT3D_FP16_SCALED ? "fp16" : "bf16", p->nx, r.c_str(), k.threads, k.lds_bytes,
+        snprintf(tmp, sizeof tmp, "scaled16 %s n=%d radices=%s(radix-16 on %s) threads=%d lds=%d planes=%ld",
+                 p->precision == FFT3D_FP16_SCALED ? "fp16" : "bf16", p->nx, r.c_str(), p->q16_valu ? "VALU" : "MFMA",
+                 k.threads, k.lds_bytes,
                  (long)p->batch * p->nz);
         d = tmp;
     } else if (p->scheme == kFused) {

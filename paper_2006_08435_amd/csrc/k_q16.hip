@@ -4,16 +4,31 @@
 
 namespace fft3d {
 
+// fmt: 1 binary16, 2 bfloat16; +16 selects the vector-ALU radix-16 stage.
+template <int N, int S, int F, bool M>
+static void plane_k(const unsigned* ip, const signed char* ie, unsigned* mp, signed char* me, const float2* tw,
+                    long planes, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_q16_plane<N, S, F, M>), dim3((unsigned)planes), dim3(Q16Geom<N>::T), 0, st, ip, ie, mp, me,
+                       tw);
+}
+
+template <int N, int S, int F, bool M>
+static void slab_k(const unsigned* mp, const signed char* me, unsigned* op, signed char* oe, const float2* tw,
+                   long slabs, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_q16_slab<N, S, F, M>), dim3((unsigned)slabs), dim3(Q16Geom<N>::T), 0, st, mp, me, op, oe,
+                       tw);
+}
+
 template <int N, int S>
 static hipError_t launch_plane(const unsigned* ip, const signed char* ie, unsigned* mp, signed char* me,
                                const float2* tw, long planes, int fmt_in, hipStream_t st)
 {
-    if (fmt_in == kFmtF16)
-        hipLaunchKernelGGL((k_q16_plane<N, S, kFmtF16>), dim3((unsigned)planes), dim3(Q16Geom<N>::T), 0, st, ip, ie,
-                           mp, me, tw);
-    else
-        hipLaunchKernelGGL((k_q16_plane<N, S, kFmtBF16>), dim3((unsigned)planes), dim3(Q16Geom<N>::T), 0, st, ip,
-                           ie, mp, me, tw);
+    const bool valu = fmt_in & 16;
+    const int f = fmt_in & 15;
+    if (f == kFmtF16) (valu ? plane_k<N, S, kFmtF16, false> : plane_k<N, S, kFmtF16, true>)(ip, ie, mp, me, tw, planes, st);
+    else (valu ? plane_k<N, S, kFmtBF16, false> : plane_k<N, S, kFmtBF16, true>)(ip, ie, mp, me, tw, planes, st);
     return hipGetLastError();
 }
 
@@ -21,12 +36,10 @@ template <int N, int S>
 static hipError_t launch_slab(const unsigned* mp, const signed char* me, unsigned* op, signed char* oe,
                               const float2* tw, long slabs, int fmt_out, hipStream_t st)
 {
-    if (fmt_out == kFmtF16)
-        hipLaunchKernelGGL((k_q16_slab<N, S, kFmtF16>), dim3((unsigned)slabs), dim3(Q16Geom<N>::T), 0, st, mp, me, op,
-                           oe, tw);
-    else
-        hipLaunchKernelGGL((k_q16_slab<N, S, kFmtBF16>), dim3((unsigned)slabs), dim3(Q16Geom<N>::T), 0, st, mp, me,
-                           op, oe, tw);
+    const bool valu = fmt_out & 16;
+    const int f = fmt_out & 15;
+    if (f == kFmtF16) (valu ? slab_k<N, S, kFmtF16, false> : slab_k<N, S, kFmtF16, true>)(mp, me, op, oe, tw, slabs, st);
+    else (valu ? slab_k<N, S, kFmtBF16, false> : slab_k<N, S, kFmtBF16, true>)(mp, me, op, oe, tw, slabs, st);
     return hipGetLastError();
 }
 

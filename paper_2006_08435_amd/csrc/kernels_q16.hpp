@@ -67,21 +67,19 @@ struct Q16Geom {
 
 // Load NR rows of N scaled16 values (row r's payload at pay + r * rstride,
 // its exponent at ex[r * estride]) and store their exact FP32 values into
-// the LDS tile (row stride RS).  All global loads are issued first.
+// the LDS tile (row stride RS).  One 4-byte payload word per lane and load,
+// consecutive lanes on consecutive points (coalesced loads, conflict-free
+// LDS stores); all global loads are issued before the first LDS store.
 template <int NR, int N, int RS, int T, int FMT>
 __device__ __forceinline__ void q16_load_tile(const unsigned* pay, long rstride, const signed char* ex, long estride,
                                               float2* lds, int* lds_e, int tid)
 {
-    static_assert(N % 4 == 0, "rows move as 16-byte units");
-    constexpr int UNITS = NR * N / 4, IT = (UNITS + T - 1) / T;
-    uint4 u[IT];
+    constexpr int UNITS = NR * N, IT = (UNITS + T - 1) / T;
+    unsigned u[IT];
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
         const int i = tid + k * T;
-        if (UNITS % T == 0 || i < UNITS) {
-            const int r = (4 * i) / N, x = (4 * i) % N;
-            u[k] = *reinterpret_cast<const uint4*>(pay + r * rstride + x);
-        }
+        if (UNITS % T == 0 || i < UNITS) u[k] = pay[(i / N) * rstride + (i % N)];
     }
     for (int r = tid; r < NR; r += T) lds_e[r] = ex[r * estride];
     __syncthreads();
@@ -89,13 +87,8 @@ __device__ __forceinline__ void q16_load_tile(const unsigned* pay, long rstride,
     for (int k = 0; k < IT; ++k) {
         const int i = tid + k * T;
         if (UNITS % T == 0 || i < UNITS) {
-            const int r = (4 * i) / N, x = (4 * i) % N;
-            const int e = lds_e[r];
-            float2* d = lds + r * RS + x;
-            d[0] = make_float2(ldexpf(dec16<FMT>(u[k].x & 0xFFFFu), e), ldexpf(dec16<FMT>(u[k].x >> 16), e));
-            d[1] = make_float2(ldexpf(dec16<FMT>(u[k].y & 0xFFFFu), e), ldexpf(dec16<FMT>(u[k].y >> 16), e));
-            d[2] = make_float2(ldexpf(dec16<FMT>(u[k].z & 0xFFFFu), e), ldexpf(dec16<FMT>(u[k].z >> 16), e));
-            d[3] = make_float2(ldexpf(dec16<FMT>(u[k].w & 0xFFFFu), e), ldexpf(dec16<FMT>(u[k].w >> 16), e));
+            const int r = i / N, x = i % N, e = lds_e[r];
+            lds[r * RS + x] = make_float2(ldexpf(dec16<FMT>(u[k] & 0xFFFFu), e), ldexpf(dec16<FMT>(u[k] >> 16), e));
         }
     }
 }
@@ -200,14 +193,16 @@ __device__ __forceinline__ void mfma_stage16(float2* lds, int tid)
 }
 
 // All stages of a length-N KIND-1 transform on an LDS tile, in place; ends
-// with a barrier.
-template <int N, int S, int L, int T, int LS, int ES>
+// with a barrier.  MFMA: radix-16 stage on the matrix cores (else the same
+// stage as an FP32 radix-16 butterfly on the vector ALUs).
+template <int N, int S, int L, int T, int LS, int ES, bool MFMA>
 __device__ __forceinline__ void q16_fft_lds(float2* lds, const float2* __restrict__ tw, int tid)
 {
     using P = Plan1D<N, 1>;
-    mfma_stage16<N, S, L, T, LS, ES>(lds, tid);
-    __syncthreads();
     const LdsAcc<LS, ES> a{lds};
+    if constexpr (MFMA) mfma_stage16<N, S, L, T, LS, ES>(lds, tid);
+    else fft_stage_p<P, 0, S, L, T, true, true>(a, a, tw, tid);
+    __syncthreads();
     if constexpr (P::stages > 1) { fft_stage_p<P, 1, S, L, T, true, true>(a, a, tw, tid); __syncthreads(); }
     if constexpr (P::stages > 2) { fft_stage_p<P, 2, S, L, T, true, true>(a, a, tw, tid); __syncthreads(); }
     if constexpr (P::stages > 3) { fft_stage_p<P, 3, S, L, T, true, true>(a, a, tw, tid); __syncthreads(); }
@@ -216,7 +211,7 @@ __device__ __forceinline__ void q16_fft_lds(float2* lds, const float2* __restric
 
 // Pass A: plane p = b * N + z.  Rows of the input (b, z, y) -> rows of the
 // FP16 intermediate (b, z, ky).
-template <int N, int S, int FMT_IN>
+template <int N, int S, int FMT_IN, bool MFMA>
 __global__ void __launch_bounds__(Q16Geom<N>::T)
 k_q16_plane(const unsigned* in_pay, const signed char* in_exp, unsigned* mid_pay, signed char* mid_exp,
             const float2* __restrict__ tw)
@@ -229,14 +224,14 @@ k_q16_plane(const unsigned* in_pay, const signed char* in_exp, unsigned* mid_pay
     const long p = blockIdx.x;
     q16_load_tile<N, N, RS, T, FMT_IN>(in_pay + p * N * N, N, in_exp + p * N, 1, lds, lds_e, tid);
     __syncthreads();
-    q16_fft_lds<N, S, N, T, RS, 1>(lds, tw, tid);   // x: lines = rows
-    q16_fft_lds<N, S, N, T, 1, RS>(lds, tw, tid);   // y: lines = columns
+    q16_fft_lds<N, S, N, T, RS, 1, MFMA>(lds, tw, tid);   // x: lines = rows
+    q16_fft_lds<N, S, N, T, 1, RS, MFMA>(lds, tw, tid);   // y: lines = columns
     q16_store_rows<N, N, RS, T, kFmtF16>(lds, mid_pay + p * N * N, N, mid_exp + p * N, 1, tid);
 }
 
 // Pass B: slab s = b * N + y; rows (b, z, y) of the intermediate for all z
 // -> rows (b, kz, y) of the output.
-template <int N, int S, int FMT_OUT>
+template <int N, int S, int FMT_OUT, bool MFMA>
 __global__ void __launch_bounds__(Q16Geom<N>::T)
 k_q16_slab(const unsigned* mid_pay, const signed char* mid_exp, unsigned* out_pay, signed char* out_exp,
            const float2* __restrict__ tw)
@@ -250,7 +245,7 @@ k_q16_slab(const unsigned* mid_pay, const signed char* mid_exp, unsigned* out_pa
     const long row0 = b * N * N + y;   // row index of (b, z = 0, y); rows of successive z are N apart
     q16_load_tile<N, N, RS, T, kFmtF16>(mid_pay + row0 * N, (long)N * N, mid_exp + row0, N, lds, lds_e, tid);
     __syncthreads();
-    q16_fft_lds<N, S, N, T, 1, RS>(lds, tw, tid);   // z: lines = x, elements along z (LDS rows)
+    q16_fft_lds<N, S, N, T, 1, RS, MFMA>(lds, tw, tid);   // z: lines = x, elements along z (LDS rows)
     q16_store_rows<N, N, RS, T, FMT_OUT>(lds, out_pay + row0 * N, (long)N * N, out_exp + row0, N, tid);
 }
 

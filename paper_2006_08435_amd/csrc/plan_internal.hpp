@@ -69,6 +69,7 @@ struct fft3d_plan_s {
     int fused_grid;            // workgroups of the persistent launch
     int fused_lag;             // dependency lag in grids
     int fused_chunk;           // items per queue claim (0: static round robin)
+    bool q16_valu;             // scaled16 plans: radix-16 stage on the vector ALUs instead of MFMA
     bool many;                 // plan from fft3d_plan_many
     fft3d::ManyPlan mp;
 };

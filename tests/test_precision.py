@@ -2,6 +2,8 @@
 per-row power-of-two exponent), FP32 arithmetic, radix-16 on the matrix
 cores.  Bars: conversions bit-exact against the oracle's encoder; transforms
 within relative L2 2e-3 of the FP64 oracle applied to the dequantized input."""
+import os
+
 import numpy as np
 import pytest
 
@@ -97,7 +99,8 @@ def test_transform_within_bound(F, n, prec, direction):
     b = 2 if n <= 64 else 1
     x = np.stack([workloads.sphere_grid(n, 900 + n + j) for j in range(b)])
     plan, pin, ein, pout, eout = run_q16(F, x, prec, direction)
-    assert "scaled16" in plan.describe() and "MFMA" in plan.describe()
+    engine = "VALU" if os.environ.get("FFT3D_Q16_VALU") == "1" else "MFMA"   # radix-16 engine chosen at plan time
+    assert "scaled16" in plan.describe() and "radix-16 on " + engine in plan.describe()
     xin = oracle.q16_decode(pin, ein, FMT[prec])        # the input IS the 16-bit data
     got = oracle.q16_decode(pout, eout, FMT[prec])
     ref = oracle.fft3d(xin, direction)
@@ -138,3 +141,16 @@ def test_batch_32x128(F, prec):
             got = oracle.q16_decode(pout[j:j + 1], eout[j:j + 1], FMT[prec])
             r = rel(got, oracle.fft3d(xin, direction))
             assert r <= TOL16, (prec, direction, j, r)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_valu_engine_within_bound(F, prec, monkeypatch):
+    """The same transform with the radix-16 stage on the vector ALUs."""
+    monkeypatch.setenv("FFT3D_Q16_VALU", "1")
+    n = 64
+    x = np.stack([workloads.sphere_grid(n, 300 + j) for j in range(2)])
+    plan, pin, ein, pout, eout = run_q16(F, x, prec, 1)
+    assert "radix-16 on VALU" in plan.describe()
+    xin = oracle.q16_decode(pin, ein, FMT[prec])
+    got = oracle.q16_decode(pout, eout, FMT[prec])
+    assert rel(got, oracle.fft3d(xin, 1)) <= TOL16
