@@ -60,6 +60,13 @@ bool env_flag(const char* name)
 
 static bool test_fail_alloc() { return env_flag("FFT3D_TEST_FAIL_ALLOC"); }
 
+// FFT3D_FUSED: 1 = persistent plane+slab kernel, 2 = its XCD-local variant.
+static int fused_mode()
+{
+    const char* e = std::getenv("FFT3D_FUSED");
+    return e ? std::atoi(e) : 0;
+}
+
 int last_error_value() { return g_last_error; }
 void clear_error() { g_last_error = FFT3D_OK; }
 
@@ -125,7 +132,7 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
         p->q16_valu = env_flag("FFT3D_Q16_VALU");
     }
     else if (nx == ny && ny == nz && nx <= kCubeMaxN) p->scheme = kCube;
-    else if (nx == ny && ny == nz && fused_fn(nx, direction) && env_flag("FFT3D_FUSED")) p->scheme = kFused;
+    else if (nx == ny && ny == nz && fused_fn(nx, direction) && fused_mode() > 0) p->scheme = kFused;
     else if (nx == ny) p->scheme = kPlaneZ;
     else p->scheme = kAxes;
 
@@ -184,7 +191,10 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
         p->passes.push_back({Pass::kQ16PlaneK, nx, B * nz, {}, p->tw_x, 0});
         p->passes.push_back({Pass::kQ16SlabK, nx, B * ny, {}, p->tw_x, 0});
     } else if (p->scheme == kFused) {
-        const size_t cb = sizeof(FusedCtl) + sizeof(unsigned) * (size_t)batch;
+        // room for either control-block layout (XcdCtl is the larger one)
+        const size_t cb = (sizeof(XcdCtl) > sizeof(FusedCtl) ? sizeof(XcdCtl) : sizeof(FusedCtl)) +
+                          sizeof(unsigned) * (size_t)batch;
+        p->ctl_bytes = cb;
         if (hipMalloc((void**)&p->ctl, cb) != hipSuccess || hipMemset(p->ctl, 0, cb) != hipSuccess) {
             (void)hipGetLastError();
             if (p->ctl) (void)hipFree(p->ctl);
@@ -201,6 +211,15 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
         p->fused_lag = (resident + nx - 1) / nx + 1;
         const char* ck = std::getenv("FFT3D_FUSED_CHUNK");
         p->fused_chunk = ck ? std::atoi(ck) : 1;
+        int nxcc = 1;
+        if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || nxcc < 1) {
+            (void)hipGetLastError();
+            nxcc = 1;
+        }
+        if (nxcc > 8) nxcc = 8;
+        if (env_flag("FFT3D_LOG")) std::fprintf(stderr, "fft3d_plan: %d XCDs, %d resident workgroups\n", nxcc, resident);
+        p->fused_xcd = fused_mode() == 2 ? nxcc : 0;
+        if (p->fused_xcd) p->fused_lag = (resident / nxcc + nx - 1) / nx + 1;
         p->passes.push_back({Pass::kFusedK, nx, B, {}, p->tw_x});
     } else if (p->scheme == kCube) {
         p->passes.push_back({Pass::kCubeK, nx, B, {}, p->tw_x});
@@ -275,6 +294,9 @@ static hipError_t run_pass(const fft3d_plan_s* p, const Pass& ps, const float2* 
         return q16_slab_fn(ps.n, S)(ip, ie, op, oe, tw, ps.count, f, st);
     }
     case Pass::kFusedK:
+        if (p->ctl_bytes < sizeof(XcdCtl) + sizeof(unsigned) * (size_t)p->batch) return hipErrorInvalidValue;
+        if (p->fused_xcd)
+            return fused_xcd_fn(ps.n, S)(src, dst, tw, p->ctl, p->batch, p->fused_lag, p->fused_grid, p->fused_xcd, st);
         return fused_fn(ps.n, S)(src, dst, tw, p->ctl, p->batch, p->fused_lag, p->fused_grid, p->fused_chunk, st);
     }
     return hipErrorInvalidValue;
@@ -420,19 +442,28 @@ int fft3d_dequantize(int precision, long rows, int row_len, const void* in, void
     return FFT3D_OK;
 }
 
+static unsigned* timeouts_ptr(fft3d_plan_t p)
+{
+    if (!p->many && p->fused_xcd) return &reinterpret_cast<XcdCtl*>(p->ctl)->timeouts;
+    return &p->ctl->timeouts;
+}
+
 int fft3d_plan_check(fft3d_plan_t p)
 {
     if (!p) return FFT3D_E_INVALID_ARG;
     if (!p->ctl) return FFT3D_OK;
     unsigned t = 0;
-    if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(&t, &p->ctl->timeouts, sizeof t, hipMemcpyDeviceToHost) != hipSuccess) {
+    const hipError_t e1 = hipDeviceSynchronize();
+    const hipError_t e2 = e1 == hipSuccess ? hipMemcpy(&t, timeouts_ptr(p), sizeof t, hipMemcpyDeviceToHost) : e1;
+    if (e2 != hipSuccess) {
+        if (env_flag("FFT3D_LOG"))
+            std::fprintf(stderr, "fft3d_plan_check: %s / %s\n", hipGetErrorString(e1), hipGetErrorString(e2));
         (void)hipGetLastError();
         return FFT3D_E_LAUNCH;
     }
     if (t) {
         const unsigned z = 0;
-        (void)hipMemcpy(&p->ctl->timeouts, &z, sizeof z, hipMemcpyHostToDevice);
+        (void)hipMemcpy(timeouts_ptr(p), &z, sizeof z, hipMemcpyHostToDevice);
         return FFT3D_E_TIMEOUT;
     }
     return FFT3D_OK;
@@ -464,8 +495,9 @@ int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
         d = tmp;
     } else if (p->scheme == kFused) {
         const KernelInfo k = fused_info(p->nx);
-        snprintf(tmp, sizeof tmp, "fused n=%d radices=%s threads=%d lds=%d grids=%d workgroups=%d lag=%d", p->nx,
-                 radices(p->nx).c_str(), k.threads, k.lds_bytes, p->batch, p->fused_grid, p->fused_lag);
+        snprintf(tmp, sizeof tmp, "fused n=%d radices=%s threads=%d lds=%d grids=%d workgroups=%d lag=%d xcd_queues=%d",
+                 p->nx, radices(p->nx).c_str(), k.threads, k.lds_bytes, p->batch, p->fused_grid, p->fused_lag,
+                 p->fused_xcd);
         d = tmp;
     } else if (p->scheme == kCube) {
         const KernelInfo k = cube_info(p->nx);

@@ -25,6 +25,27 @@ static int occupancy()
     return nb > 0 ? nb : 1;
 }
 
+template <int N, int S>
+static hipError_t launch_fused_xcd(const float2* in, float2* out, const float2* tw, FusedCtl* ctl, int batch, int lag,
+                                   int grid, int q, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_fused_xcd<N, S>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out, tw,
+                       reinterpret_cast<XcdCtl*>(ctl), batch, q, lag);
+    return hipGetLastError();
+}
+
+#define FFT3D_FUSED_XCD_CASE(n)                                                \
+    case n:                                                                    \
+        return sign < 0 ? &launch_fused_xcd<n, -1> : &launch_fused_xcd<n, 1>;
+
+FusedXcdFn fused_xcd_fn(int n, int sign)
+{
+    switch (n) {
+        FFT3D_FOR_EACH_FUSED_SIZE(FFT3D_FUSED_XCD_CASE)
+    default: return nullptr;
+    }
+}
+
 #define FFT3D_FUSED_CASE(n)                                                    \
     case n:                                                                    \
         return sign < 0 ? &launch_fused<n, -1> : &launch_fused<n, 1>;

@@ -508,6 +508,97 @@ k_fused(const float2* in, float2* out, const float2* __restrict__ tw, FusedCtl* 
     }
 }
 
+// XCD-local form of the fused kernel.  Each XCD (accelerator complex die,
+// with its own L2) owns the grids g with g mod Q == its XCC id mod Q and has
+// its own item queue, so a grid's planes and slabs are transformed by
+// workgroups that share one L2: the intermediate is stored and loaded with
+// ordinary cached accesses, and a plane item is published once its stores
+// have completed into that L2.  The last workgroup to leave checks that every
+// queue was fully claimed (an XCD without workgroups would leave its grids
+// untransformed; that is reported through the timeout counter).
+struct XcdCtl {
+    unsigned head[8][32];   // one queue counter per XCD, 128 bytes apart
+    unsigned exited;
+    unsigned timeouts;
+    unsigned pad[30];
+    unsigned done[1];       // per grid: plane items completed
+};
+
+__device__ __forceinline__ unsigned xcc_id()
+{
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);   // HW_REG_XCC_ID[3:0]
+}
+
+template <int N, int S>
+__global__ void __launch_bounds__(PlaneGeom<N>::T)
+k_fused_xcd(const float2* in, float2* out, const float2* __restrict__ tw, XcdCtl* ctl, int batch, int q, int lag)
+{
+    constexpr int T = PlaneGeom<N>::T;
+    constexpr long V = (long)N * N * N;
+    __shared__ float2 lds[PlaneGeom<N>::WORDS];
+    __shared__ int item_sh;
+    const int tid = threadIdx.x;
+    const int x = (int)(xcc_id() % (unsigned)q);
+    const int bq = (batch - x + q - 1) / q;     // grids of this XCD's queue
+    const long total = 2L * bq * N;
+    int pending = -1;
+    auto publish = [&]() {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (pending >= 0 && tid == 0)
+            __hip_atomic_fetch_add(&ctl->done[pending], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pending = -1;
+    };
+    for (;;) {
+        if (tid == 0) item_sh = (int)atomicAdd(&ctl->head[x][0], 1u);
+        __syncthreads();
+        const long it = item_sh;
+        if (it >= total) break;
+        const Item w = decode_item(it, N, bq, lag);
+        const int g = w.g * q + x;
+        if (!w.slab) {
+            const long base = g * V + (long)w.idx * N * N;
+            constexpr int RS = PlaneGeom<N>::RS;
+            tile_to_lds<N, N, RS, T>(in + base, lds, tid);
+            publish();
+            fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
+            const LdsAcc<1, RS> col{lds};
+            const PlaneColOut<N, false> dst{out + base};
+            run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
+            pending = g;
+        } else {
+            publish();
+            if (tid == 0) {
+                unsigned n = 0;
+                while (__hip_atomic_load(&ctl->done[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)N) {
+                    if (++n >= kSpinLimit) {
+                        atomicAdd(&ctl->timeouts, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            __syncthreads();
+            const long base = g * V + (long)w.idx * N;
+            slab_body<N, S, T, false>(out + base, out + base, (long)N * N, tw, lds, tid);
+        }
+        __syncthreads();
+    }
+    publish();
+    if (tid == 0) {
+        const unsigned prev = __hip_atomic_fetch_add(&ctl->exited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gridDim.x - 1) {
+            for (int y = 0; y < q; ++y) {
+                const int by = (batch - y + q - 1) / q;
+                if (ctl->head[y][0] < (unsigned)(2L * by * N)) atomicAdd(&ctl->timeouts, 1u);   // queue not drained
+                ctl->head[y][0] = 0;
+            }
+            for (int gg = 0; gg < batch; ++gg) ctl->done[gg] = 0;
+            __hip_atomic_store(&ctl->exited, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 // ---------------------------------------------------------- strided axis --
 
 // Lines are enumerated (o, x), x fastest; line li has global base

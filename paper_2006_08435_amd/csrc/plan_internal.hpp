@@ -66,9 +66,11 @@ struct fft3d_plan_s {
     int pf_grid;               // workgroups of the persistent plane pass (nx == ny plans)
     std::vector<fft3d::Pass> passes;
     fft3d::FusedCtl* ctl;      // persistent-kernel control block (fused / many)
+    size_t ctl_bytes;          // its allocated size
     int fused_grid;            // workgroups of the persistent launch
     int fused_lag;             // dependency lag in grids
     int fused_chunk;           // items per queue claim (0: static round robin)
+    int fused_xcd;             // > 0: XCD-local variant with this many queues
     bool q16_valu;             // scaled16 plans: radix-16 stage on the vector ALUs instead of MFMA
     bool many;                 // plan from fft3d_plan_many
     fft3d::ManyPlan mp;

@@ -38,6 +38,10 @@ int plane_pf_blocks_per_cu(int n);
 AxisStrFn axis_str_fn(int n, int sign);
 AxisRowFn axis_row_fn(int n, int sign);
 FusedFn fused_fn(int n, int sign);
+// XCD-local variant; the control block is an XcdCtl (larger than FusedCtl).
+using FusedXcdFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, FusedCtl* ctl, int batch, int lag,
+                                  int grid, int q, hipStream_t st);
+FusedXcdFn fused_xcd_fn(int n, int sign);
 // Workgroups of the fused kernel that fit on one compute unit at once.
 int fused_blocks_per_cu(int n);
 

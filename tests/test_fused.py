@@ -136,3 +136,25 @@ def test_graph_capture_replays_match_eager(fft3d, fused, monkeypatch):
     from paper_2006_08435_amd import _lib
     assert _lib.lib().fft3d_plan_check(fwd.handle) == 0
     assert _lib.lib().fft3d_plan_check(inv.handle) == 0
+
+
+@pytest.mark.parametrize("n,batch", [(128, 16), (64, 16), (96, 8), (48, 24), (128, 10), (32, 3)])
+def test_xcd_local_variant(fft3d, n, batch, monkeypatch):
+    """FFT3D_FUSED=2: every XCD owns whole grids (its own queue); checked
+    against the oracle, for repeats, and by the drained-queue health check."""
+    monkeypatch.setenv("FFT3D_FUSED", "2")
+    x = workloads.uniform_grid(n, 7 * n + batch, batch=batch)
+    plan = fft3d.Plan(n, n, n, batch, "fp32", 1)
+    assert "xcd_queues=" in plan.describe() and "xcd_queues=0" not in plan.describe(), plan.describe()
+    xt = torch.from_numpy(x).cuda()
+    first = plan.exec(xt).clone()
+    out = torch.empty_like(xt)
+    for _ in range(5):
+        plan.exec(xt, out)
+    torch.cuda.synchronize()
+    assert torch.equal(first, out)
+    got = first.cpu().numpy()
+    for j in sorted({0, batch // 2, batch - 1}):
+        assert rel(got[j], oracle.fft3d(x[j].astype(np.complex128), 1)) <= TOL, (n, batch, j)
+    from paper_2006_08435_amd import _lib
+    assert _lib.lib().fft3d_plan_check(plan.handle) == 0
