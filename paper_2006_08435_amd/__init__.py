@@ -59,6 +59,12 @@ class Plan:
         _lib.lib().fft3d_plan_describe(self._h, buf, 512)
         return buf.value.decode()
 
+    def set_cutoff(self, r2: float) -> None:
+        """Promise that the input vanishes wherever Gx^2+Gy^2+Gz^2 >= r2
+        (signed frequencies) and prune the inverse accordingly; r2 <= 0
+        restores the dense schedule (``fft3d_plan_set_cutoff``)."""
+        _lib.check(_lib.lib().fft3d_plan_set_cutoff(self._h, float(r2)), "fft3d_plan_set_cutoff")
+
     def exec_ptr(self, in_ptr: int, out_ptr: int, stream_handle: int) -> None:
         _lib.check(_lib.lib().fft3d_exec(self._h, in_ptr, out_ptr, stream_handle), "fft3d_exec")
 

@@ -41,6 +41,7 @@ SIGNATURES = {
     "fft3d_plan_describe": (_ci, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "fft3d_plan_passes": (_ci, [_vp]),
     "fft3d_plan_check": (_ci, [_vp]),
+    "fft3d_plan_set_cutoff": (_ci, [_vp, ctypes.c_double]),
     "fft3d_quantize": (_ci, [_ci, ctypes.c_long, _ci, _vp, _vp, _vp]),
     "fft3d_dequantize": (_ci, [_ci, ctypes.c_long, _ci, _vp, _vp, _vp]),
     "fft3d_plan_many": (_vp, [_ci, _vp, _vp, _vp, _vp, _ci, _ci]),

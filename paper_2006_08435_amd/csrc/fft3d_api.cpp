@@ -252,6 +252,7 @@ int fft3d_destroy(fft3d_plan_t p)
     if (p->mp.d_grids) (void)hipFree(p->mp.d_grids);
     if (p->mp.d_items) (void)hipFree(p->mp.d_items);
     if (p->mp.d_twoff) (void)hipFree(p->mp.d_twoff);
+    if (p->d_zlist) (void)hipFree(p->d_zlist);
     delete p;
     return FFT3D_OK;
 }
@@ -282,6 +283,9 @@ static hipError_t run_pass(const fft3d_plan_s* p, const Pass& ps, const float2* 
         return plane_pf_fn(ps.n, S)(src, dst, tw, ps.count, ps.grid, 0, nullptr, nullptr, 1, st);
     case Pass::kRowK: return axis_row_fn(ps.n, S)(src, dst, tw, ps.count, st);
     case Pass::kStrK: return axis_str_fn(ps.n, S)(src, dst, tw, ps.map, 0, nullptr, nullptr, 0, st);
+    case Pass::kPlanePrunedK:
+        return plane_pruned_fn(ps.n, S)(src, dst, tw, ps.count, ps.grid, p->d_zlist, p->n_zlist, p->nz, p->cut_r2, st);
+    case Pass::kStrPrunedK: return axis_str_pruned_fn(ps.n, S)(src, dst, tw, ps.map, p->cut_r2, st);
     case Pass::kQ16PlaneK:
     case Pass::kQ16SlabK: {
         const size_t pay = (size_t)p->batch * p->vol * 4;
@@ -469,7 +473,56 @@ int fft3d_plan_check(fft3d_plan_t p)
     return FFT3D_OK;
 }
 
-int many_describe(fft3d_plan_t p, char* buf, size_t len);
+int fft3d_plan_set_cutoff(fft3d_plan_t p, double r2)
+{
+    if (!p) return FFT3D_E_INVALID_ARG;
+    if (!(r2 == r2)) return FFT3D_E_INVALID_ARG;   // NaN
+    if (p->many || p->precision != FFT3D_FP32 || p->direction != FFT3D_INVERSE || p->nx != p->ny)
+        return FFT3D_E_UNSUPPORTED;
+    const int nx = p->nx, nz = p->nz;
+    if (!plane_pruned_fn(nx, p->direction) || !axis_str_pruned_fn(nz, p->direction)) return FFT3D_E_UNSUPPORTED;
+    if (p->dense_passes.empty()) p->dense_passes = p->passes;
+    if (r2 <= 0) {
+        p->passes = p->dense_passes;
+        p->cut_r2 = 0;
+        p->n_zlist = 0;
+        return FFT3D_OK;
+    }
+    // planes kz whose signed frequency satisfies Gz^2 < r2, in ascending kz;
+    // the z pass applies the same test element by element
+    std::vector<int> zl;
+    for (int k = 0; k < nz; ++k) {
+        const int g = signed_freq(k, nz);
+        if ((double)(g * g) < r2) zl.push_back(k);
+    }
+    int* d = nullptr;
+    if (test_fail_alloc() || hipMalloc((void**)&d, sizeof(int) * zl.size()) != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_ALLOC;
+    }
+    if (hipMemcpy(d, zl.data(), sizeof(int) * zl.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(d);
+        return FFT3D_E_LAUNCH;
+    }
+    if (p->d_zlist) (void)hipFree(p->d_zlist);
+    p->d_zlist = d;
+    p->n_zlist = (int)zl.size();
+    p->cut_r2 = r2;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1) {
+        (void)hipGetLastError();
+        cus = 1;
+    }
+    const long planes = (long)p->batch * p->n_zlist;
+    const long resident = (long)plane_pf_blocks_per_cu(nx) * cus;
+    const long B = p->batch;
+    const AxisMap zmap{B * p->ny * nx, nx, p->ny, p->vol, (long)nx, (long)nx * p->ny};
+    p->passes.clear();
+    p->passes.push_back({Pass::kPlanePrunedK, nx, planes, {}, p->tw_x, (int)(planes < resident ? planes : resident)});
+    if (nz > 1) p->passes.push_back({Pass::kStrPrunedK, nz, 0, zmap, p->tw_z, 0});
+    return FFT3D_OK;
+}
 
 int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
 {
@@ -517,10 +570,15 @@ int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
         d = tmp;
     }
     d += p->direction < 0 ? " forward" : " inverse";
+    if (p->cut_r2 > 0) {
+        snprintf(tmp, sizeof tmp, " cutoff_r2=%.17g zplanes=%d", p->cut_r2, p->n_zlist);
+        d += tmp;
+    }
     d += " kernels=";
     for (size_t i = 0; i < p->passes.size(); ++i) {
-        static const char* names[] = {"k_cube", "k_plane", "k_plane_pf", "k_axis_row", "k_axis_str", "k_fused",
-                                      "k_q16_plane", "k_q16_slab"};
+        static const char* names[] = {"k_cube",      "k_plane",    "k_plane_pf",     "k_axis_row",
+                                      "k_axis_str",  "k_fused",    "k_q16_plane",    "k_q16_slab",
+                                      "k_plane_pruned", "k_axis_str_pruned"};
         d += (i ? "," : "") + std::string(names[p->passes[i].kind]);
     }
     if (buf && len) {

@@ -373,6 +373,10 @@ int fft3d_plan_tune(fft3d_plan_t p)
     return tune(p);
 }
 
+}  // extern "C"
+
+namespace fft3d {
+
 int many_describe(fft3d_plan_t p, char* buf, size_t len)
 {
     std::ostringstream d;
@@ -389,4 +393,4 @@ int many_describe(fft3d_plan_t p, char* buf, size_t len)
     return (int)s.size();
 }
 
-}  // extern "C"
+}  // namespace fft3d

@@ -35,11 +35,33 @@ static hipError_t launch_axis_str(const float2* in, float2* out, const float2* t
     const long blocks = axis_str_blocks(m.lines);
     if (energy)
         hipLaunchKernelGGL((k_axis_str<N, S, kAxisLines, true>), dim3((unsigned)blocks),
-                           dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, out, tw, m, V, partials, vol);
+                           dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, out, tw, m, V, partials, vol, 0.0);
     else
         hipLaunchKernelGGL((k_axis_str<N, S, kAxisLines, false>), dim3((unsigned)blocks),
-                           dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, out, tw, m, V, partials, vol);
+                           dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, out, tw, m, V, partials, vol, 0.0);
     return hipGetLastError();
+}
+
+template <int N, int S>
+static hipError_t launch_axis_str_pruned(const float2* in, float2* out, const float2* tw, const AxisMap& m, double R2,
+                                         hipStream_t st)
+{
+    const long blocks = axis_str_blocks(m.lines);
+    hipLaunchKernelGGL((k_axis_str<N, S, kAxisLines, false, true>), dim3((unsigned)blocks),
+                       dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, out, tw, m, nullptr, nullptr, 0L, R2);
+    return hipGetLastError();
+}
+
+#define FFT3D_STR_PRUNED_CASE(n)                                               \
+    case n:                                                                    \
+        return sign < 0 ? &launch_axis_str_pruned<n, -1> : &launch_axis_str_pruned<n, 1>;
+
+AxisStrPrunedFn axis_str_pruned_fn(int n, int sign)
+{
+    switch (n) {
+        FFT3D_FOR_EACH_SIZE(FFT3D_STR_PRUNED_CASE)
+    default: return nullptr;
+    }
 }
 
 template <int N, int S>

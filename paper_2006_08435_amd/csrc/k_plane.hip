@@ -59,6 +59,27 @@ int plane_pf_blocks_per_cu(int n)
     }
 }
 
+template <int N, int S>
+static hipError_t launch_plane_pruned(const float2* in, float2* out, const float2* tw, long planes, int grid,
+                                      const int* zlist, int nzp, int nz, double R2, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_plane_pruned<N, S>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out, tw, planes,
+                       zlist, nzp, nz, R2);
+    return hipGetLastError();
+}
+
+#define FFT3D_PLANE_PRUNED_CASE(n)                                             \
+    case n:                                                                    \
+        return sign < 0 ? &launch_plane_pruned<n, -1> : &launch_plane_pruned<n, 1>;
+
+PlanePrunedFn plane_pruned_fn(int n, int sign)
+{
+    switch (n) {
+        FFT3D_FOR_EACH_SIZE(FFT3D_PLANE_PRUNED_CASE)
+    default: return nullptr;
+    }
+}
+
 #define FFT3D_PLANE_CASE(n)                                                    \
     case n:                                                                    \
         return sign < 0 ? &launch_plane<n, -1> : &launch_plane<n, 1>;

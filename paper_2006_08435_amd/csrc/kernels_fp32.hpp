@@ -136,6 +136,22 @@ struct TileRegs {
             if (UNITS % T == 0 || i < UNITS) r[k] = gu[i];
         }
     }
+    // Load with a row predicate: rows for which row_ok(row) is false are not
+    // read and hold zeros.
+    template <class RowOk>
+    __device__ __forceinline__ void load_rows(const float2* g, int tid, const RowOk& row_ok)
+    {
+        const U* gu = reinterpret_cast<const U*>(g);
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (UNITS % T == 0 || i < UNITS) {
+                const int row = PAIRS ? (2 * i) / ROW : i / ROW;
+                if (row_ok(row)) r[k] = gu[i];
+                else r[k] = U{};
+            }
+        }
+    }
     // Load the real factors f[e] matching this tile's elements (same unit
     // pattern: pairs of floats for even rows, single floats otherwise).
     template <class FR>
@@ -357,6 +373,49 @@ k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long pl
         fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
         const LdsAcc<1, RS> col{lds};
         const PlaneColOut<N> dst{out + p * N * N};
+        run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
+        __syncthreads();
+    }
+}
+
+// Signed frequency of index k on a length-n axis (k for k < n/2, k - n above).
+__host__ __device__ __forceinline__ int signed_freq(int k, int n) { return 2 * k < n ? k : k - n; }
+
+// Pass A of the pruned inverse: the input vanishes outside the sphere
+// |G|^2 < R2 (G = signed frequencies).  Grids are [batch][nz][N][N]; only the
+// planes kz of zlist (those with Gz^2 < R2, nzp of them) are transformed, and in each only the rows with
+// Gy^2 + Gz^2 < R2 are read; the other rows of a plane are zeros.  Planes
+// outside zlist are neither read nor written (pass B treats them as zeros).
+template <int N, int S>
+__global__ void __launch_bounds__(PlaneGeom<N>::T)
+k_plane_pruned(const float2* in, float2* out, const float2* __restrict__ tw, long planes, const int* __restrict__ zlist,
+               int nzp, int nz, double R2)
+{
+    constexpr int T = PlaneGeom<N>::T, RS = PlaneGeom<N>::RS;
+    __shared__ float2 lds[PlaneGeom<N>::WORDS];
+    const int tid = threadIdx.x;
+    TileRegs<N, N, T> regs;
+    auto plane_base = [&](long i) {
+        const long b = i / nzp;
+        return (b * nz + zlist[i % nzp]) * (long)N * N;
+    };
+    auto rows_of = [&](long i) {
+        const int gz = signed_freq(zlist[i % nzp], nz);
+        return [gz, R2](int y) {
+            const int gy = signed_freq(y, N);
+            return (double)(gy * gy + gz * gz) < R2;
+        };
+    };
+    long p = blockIdx.x;
+    if (p < planes) regs.load_rows(in + plane_base(p), tid, rows_of(p));
+    for (; p < planes; p += gridDim.x) {
+        regs.template store_lds<RS>(lds, tid);
+        __syncthreads();
+        const long pn = p + gridDim.x;
+        if (pn < planes) regs.load_rows(in + plane_base(pn), tid, rows_of(pn));
+        fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
+        const LdsAcc<1, RS> col{lds};
+        const PlaneColOut<N> dst{out + plane_base(p)};
         run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
         __syncthreads();
     }
@@ -649,13 +708,32 @@ __device__ __forceinline__ double block_sum(double x, double* red, int tid)
     return t;
 }
 
+// Strided global access whose element e reads as zero unless its signed
+// frequency satisfies G^2 < R2 (the z pass of the pruned inverse: planes
+// outside the sphere's z-range were never written by pass A).
+struct GlobStridedPruned {
+    const float2* src;
+    float2* dst;
+    long es;
+    int n;
+    double R2;
+    __device__ __forceinline__ float2 load(int, int e) const
+    {
+        const int g = signed_freq(e, n);
+        return (double)(g * g) < R2 ? src[(long)e * es] : make_float2(0.f, 0.f);
+    }
+    __device__ __forceinline__ void store(int, int e, float2 v) const { dst[(long)e * es] = v; }
+};
+
 // ENERGY: the pass is the last one of an inverse transform psi = IFFT(c);
 // while storing psi it accumulates sum V |psi|^2 and writes one FP64 partial
 // per workgroup to partials[blockIdx.x] (V indexed by position in the grid).
-template <int N, int S, int L, bool ENERGY = false>
+// PRUNE (z pass of the pruned inverse): stage-0 loads of elements whose
+// signed frequency has G^2 >= R2 are skipped (zeros).
+template <int N, int S, int L, bool ENERGY = false, bool PRUNE = false>
 __global__ void __launch_bounds__((AxisGeom<N, L>::T))
 k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap m, const float* __restrict__ V,
-           double* __restrict__ partials, long vol)
+           double* __restrict__ partials, long vol, double R2 = 0.0)
 {
     using G = AxisGeom<N, L>;
     using P = Plan1D<N>;
@@ -687,6 +765,16 @@ k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap
         }
         const double t = block_sum<T>(eg.acc, red, tid);
         if (tid == 0) partials[blockIdx.x] = t;
+    } else if constexpr (PRUNE) {
+        const GlobStridedPruned gp{in + gbase, out + gbase, m.es, N, R2};
+        if constexpr (P::stages == 1) {
+            fft_stage<N, 0, S, L, T, true, false>(gp, g, tw, tid, valid);
+        } else {
+            const LdsAcc<1, G::LP> a{lds};
+            fft_stage<N, 0, S, L, T, true, false>(gp, a, tw, tid, valid);
+            __syncthreads();
+            run_tail<N, S, L, T, 1, false>(a, g, tw, tid, valid);
+        }
     } else {
         if constexpr (P::stages == 1) {
             fft_stage<N, 0, S, L, T, true, false>(g, g, tw, tid, valid);

@@ -23,7 +23,7 @@ std::vector<float2> twiddles(int n, int sign, int kind = 0);
 // One kernel launch of an exec.  The first pass reads the caller's input,
 // every later pass works in place on the output buffer.
 struct Pass {
-    enum Kind { kCubeK, kPlaneK, kPlanePfK, kRowK, kStrK, kFusedK, kQ16PlaneK, kQ16SlabK } kind;
+    enum Kind { kCubeK, kPlaneK, kPlanePfK, kRowK, kStrK, kFusedK, kQ16PlaneK, kQ16SlabK, kPlanePrunedK, kStrPrunedK } kind;
     int n;        // transform length of this pass
     long count;   // grids / planes / rows (cube, plane, row kinds)
     AxisMap map;  // strided kind
@@ -72,6 +72,15 @@ struct fft3d_plan_s {
     int fused_chunk;           // items per queue claim (0: static round robin)
     int fused_xcd;             // > 0: XCD-local variant with this many queues
     bool q16_valu;             // scaled16 plans: radix-16 stage on the vector ALUs instead of MFMA
+    double cut_r2;             // > 0: sphere cutoff of the pruned inverse (fft3d_plan_set_cutoff)
+    int* d_zlist;              // z-planes with Gz^2 < cut_r2 (device), n_zlist of them
+    int n_zlist;
+    std::vector<fft3d::Pass> dense_passes;   // schedule without the cutoff
     bool many;                 // plan from fft3d_plan_many
     fft3d::ManyPlan mp;
 };
+
+namespace fft3d {
+// fft3d_plan_describe text of a plan from fft3d_plan_many.
+int many_describe(fft3d_plan_t p, char* buf, size_t len);
+}  // namespace fft3d

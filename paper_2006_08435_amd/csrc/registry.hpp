@@ -34,6 +34,15 @@ long axis_str_blocks(long lines);
 hipError_t launch_sum_partials(const double* partials, long n, double* out, hipStream_t st);
 PlaneFn plane_fn(int n, int sign);
 PlanePfFn plane_pf_fn(int n, int sign);
+// Pruned inverse (input vanishing outside |G|^2 < R2): pass A over the
+// planes of zlist only, reading only rows inside the sphere; pass B with
+// zero loads for planes outside it.
+using PlanePrunedFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, int grid,
+                                     const int* zlist, int nzp, int nz, double R2, hipStream_t st);
+using AxisStrPrunedFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, const AxisMap& m, double R2,
+                                       hipStream_t st);
+PlanePrunedFn plane_pruned_fn(int n, int sign);
+AxisStrPrunedFn axis_str_pruned_fn(int n, int sign);
 int plane_pf_blocks_per_cu(int n);
 AxisStrFn axis_str_fn(int n, int sign);
 AxisRowFn axis_row_fn(int n, int sign);

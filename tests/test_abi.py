@@ -38,6 +38,17 @@ def test_every_declared_symbol_is_exported():
     assert names <= set(L.SIGNATURES), names - set(L.SIGNATURES)
 
 
+def test_no_undeclared_c_exports():
+    """Every unmangled symbol the library defines is a declared entry point."""
+    import subprocess
+    L = _lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    plain = {ln.split()[-1] for ln in out.splitlines() if ln.split() and ln.split()[1] in "TtWw"}
+    plain = {n for n in plain if not n.startswith("_")}
+    assert plain == declared_functions(), plain ^ declared_functions()
+
+
 @pytest.mark.parametrize("args,code", [
     ((0, 16, 16, 1, 0, -1), -1), ((-1, 16, 16, 1, 0, -1), -1), ((16, 16, 16, 0, 0, -1), -1),
     ((16, 16, 16, -3, 0, -1), -1), ((16, 16, 16, 1, 3, -1), -1), ((16, 16, 16, 1, -1, -1), -1),
@@ -58,6 +69,7 @@ def test_null_handles():
     assert lib.fft3d_buffer_bytes(None) == 0
     assert lib.fft3d_exec(None, None, None, None) == -1
     assert lib.fft3d_plan_describe(None, None, 0) == -1
+    assert lib.fft3d_plan_set_cutoff(None, 10.0) == -1
 
 
 def test_strerror_covers_codes():
