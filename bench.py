@@ -387,8 +387,9 @@ def bench_energy(args):
 
 
 def bench_pruned(args):
-    """32 x 128^3 sphere-cutoff coefficients (|G| < N/4): the pruned inverse
-    against the dense inverse on the same input."""
+    """32 x 128^3 sphere-cutoff coefficients (|G| < N/4): pruned inverse then
+    pruned forward (the two transforms around a local-operator product),
+    against the dense inverse and forward on the same data."""
     import numpy as np
     import torch
     import oracle
@@ -399,62 +400,95 @@ def bench_pruned(args):
     r2 = (n / 4.0) ** 2
     x = workloads.sphere_batch(n, [workloads.SEED_BATCH128 + j for j in range(B)])
     xt = torch.from_numpy(x).cuda()
-    dense_out = torch.empty_like(xt)
-    out = torch.empty_like(xt)
-    dense = fft3d.Plan(n, n, n, B, "fp32", fft3d.FFT3D_INVERSE)
-    plan = fft3d.Plan(n, n, n, B, "fp32", fft3d.FFT3D_INVERSE)
-    plan.set_cutoff(r2)
+    psi = torch.empty_like(xt)
+    back = torch.empty_like(xt)
+    d_psi = torch.empty_like(xt)
+    d_back = torch.empty_like(xt)
+    plans = {}
+    for name, d in (("inverse", fft3d.FFT3D_INVERSE), ("forward", fft3d.FFT3D_FORWARD)):
+        plans["dense_" + name] = fft3d.Plan(n, n, n, B, "fp32", d)
+        plans[name] = fft3d.Plan(n, n, n, B, "fp32", d)
+        plans[name].set_cutoff(r2)
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
     L = _lib.lib()
-    pruned_ms = _time(lambda: plan.exec_ptr(xt.data_ptr(), out.data_ptr(), sh), args.steps, args.warmup, stream)
-    dense_ms = _time(lambda: dense.exec_ptr(xt.data_ptr(), dense_out.data_ptr(), sh), args.steps, args.warmup,
-                     stream)
-    pass_ms = []
-    for k in range(L.fft3d_plan_passes(plan.handle)):
-        src = xt if k == 0 else out
-        pass_ms.append(_time(lambda: _lib.check(L.fft3d_exec_pass(plan.handle, k, src.data_ptr(), out.data_ptr(),
-                                                                  sh)), args.steps, args.warmup, stream))
-    plan.exec_ptr(xt.data_ptr(), out.data_ptr(), sh)
-    dense.exec_ptr(xt.data_ptr(), dense_out.data_ptr(), sh)
+
+    def pruned_step():
+        plans["inverse"].exec_ptr(xt.data_ptr(), psi.data_ptr(), sh)
+        plans["forward"].exec_ptr(psi.data_ptr(), back.data_ptr(), sh)
+
+    def dense_step():
+        plans["dense_inverse"].exec_ptr(xt.data_ptr(), d_psi.data_ptr(), sh)
+        plans["dense_forward"].exec_ptr(d_psi.data_ptr(), d_back.data_ptr(), sh)
+
+    pruned_ms = _time(pruned_step, args.steps, args.warmup, stream)
+    dense_ms = _time(dense_step, args.steps, args.warmup, stream)
+    times = {}
+    for name, src, dst in (("inverse", xt, psi), ("forward", psi, back)):
+        pl = plans[name]
+        times[name] = _time(lambda: pl.exec_ptr(src.data_ptr(), dst.data_ptr(), sh), args.steps, args.warmup,
+                            stream)
+        times["dense_" + name] = _time(lambda: plans["dense_" + name].exec_ptr(src.data_ptr(), d_back.data_ptr(),
+                                                                               sh), args.steps, args.warmup, stream)
+        for k in range(L.fft3d_plan_passes(pl.handle)):
+            s_ = src if k == 0 else dst
+            times["%s_pass%d" % (name, k)] = _time(
+                lambda: _lib.check(L.fft3d_exec_pass(pl.handle, k, s_.data_ptr(), dst.data_ptr(), sh)),
+                args.steps, args.warmup, stream)
+    pruned_step()
+    dense_step()
     torch.cuda.synchronize()
-    equal = bool(torch.equal(out, dense_out))
-    worst = 0.0
+    g = workloads.signed_freq(n)
+    sphere = (g[:, None, None] ** 2 + g[None, :, None] ** 2 + g[None, None, :] ** 2) < r2
+    ms = torch.from_numpy(np.broadcast_to(sphere[None], x.shape).copy()).cuda()
+    fdiff = float((back[ms] - d_back[ms]).abs().max() / d_back[ms].abs().max())
+    equal = {"inverse_bitwise": bool(torch.equal(psi, d_psi)),
+             "forward_inside_sphere_max_abs_diff_over_max": fdiff}
+    worst = {"inverse": 0.0, "round_trip_inside_sphere": 0.0}
     for j in (0, B - 1):
         ref = oracle.fft3d(x[j].astype(np.complex128), 1)
-        y = out[j].cpu().numpy()
-        worst = max(worst, float(np.linalg.norm(y - ref) / np.linalg.norm(ref)))
-    # algorithmic bytes of the pruned schedule, per grid
-    g = workloads.signed_freq(n)
+        y = psi[j].cpu().numpy()
+        worst["inverse"] = max(worst["inverse"], float(np.linalg.norm(y - ref) / np.linalg.norm(ref)))
+        rt = back[j].cpu().numpy()[sphere] / n ** 3
+        worst["round_trip_inside_sphere"] = max(worst["round_trip_inside_sphere"],
+                                                float(np.linalg.norm(rt - x[j][sphere]) /
+                                                      np.linalg.norm(x[j][sphere])))
+    # algorithmic bytes per grid of each pruned pass
     zin = (g * g) < r2
-    rows = int(((g[:, None] ** 2 + g[None, :] ** 2) < r2).sum())
-    nzp = int(zin.sum())
-    a_bytes = 8.0 * (rows * n + nzp * n * n) * B
-    b_bytes = 8.0 * (nzp * n * n + n ** 3) * B
-    flops = 5.0 * n ** 3 * math.log2(n ** 3) * B
+    disk = int(((g[:, None] ** 2 + g[None, :] ** 2) < r2).sum())   # x-rows (inverse) = z-lines (forward)
+    nzp, nsph = int(zin.sum()), int(sphere.sum())
+    pass_bytes = {"inverse_pass0": 8.0 * (disk * n + nzp * n * n) * B,
+                  "inverse_pass1": 8.0 * (nzp * n * n + n ** 3) * B,
+                  "forward_pass0": 8.0 * (n ** 3 + disk * n) * B,
+                  "forward_pass1": 8.0 * (disk * n + nsph) * B}
+    total = sum(pass_bytes.values())
+    flops = 2 * 5.0 * n ** 3 * math.log2(n ** 3) * B
     rec = _base_record(flops / (pruned_ms * 1e-3) / 1e9, "GFLOP/s", args, pruned_ms,
-                       "pruned c2c 3D FFT inverse of sphere-cutoff coefficients (|G| < N/4), 32 grids of 128^3, "
-                       "complex64; GFLOP/s counts the dense 5N^3log2N^3 per grid",
+                       "pruned c2c 3D FFT, sphere-cutoff coefficients (|G| < N/4), 32 grids of 128^3: inverse then "
+                       "forward, complex64; GFLOP/s counts the dense 5N^3log2N^3 per transform",
                        {"n": n, "batch": B, "cutoff_r2": r2, "precision": "fp32",
                         "input": "sphere-cutoff plane-wave coefficients"})
-    dom = int(np.argmax(pass_ms))
-    dom_bytes = (a_bytes, b_bytes)[dom]
-    achieved = dom_bytes / (pass_ms[dom] * 1e-3) / 1e9
+    pk = [k for k in pass_bytes]
+    dom = max(pk, key=lambda k: times[k])
+    achieved = pass_bytes[dom] / (times[dom] * 1e-3) / 1e9
+    kern = {"inverse_pass0": "k_plane_pruned<128,1,false>", "inverse_pass1": "k_axis_str<128,1,64,false,1>",
+            "forward_pass0": "k_plane_pruned<128,-1,true>", "forward_pass1": "k_axis_str<128,-1,64,false,2>"}
     rec.update({
-        "times_ms": {"pruned_inverse": round(pruned_ms, 4), "dense_inverse": round(dense_ms, 4),
-                     "speedup": round(dense_ms / pruned_ms, 3),
-                     "passes": [round(t, 4) for t in pass_ms]},
-        "sphere": {"nonzero_planes": nzp, "nonzero_rows_per_grid": rows, "rows_per_grid": n * n},
-        "algorithmic_bytes": {"pruned": a_bytes + b_bytes, "dense": 4.0 * 8 * n ** 3 * B},
-        "hbm_gbs_algorithmic": round((a_bytes + b_bytes) / (pruned_ms * 1e-3) / 1e9, 1),
-        "equal_to_dense_inverse": equal,
-        "rel_l2_vs_fp64": {"max_over_sampled_grids": worst, "sampled": [0, B - 1]},
-        "plans": {"pruned": plan.describe(), "dense": dense.describe()},
+        "times_ms": dict({"pruned_step": round(pruned_ms, 4), "dense_step": round(dense_ms, 4),
+                          "speedup": round(dense_ms / pruned_ms, 3)},
+                         **{k: round(v, 4) for k, v in times.items()}),
+        "sphere": {"nonzero_planes": nzp, "disk_lines_per_grid": disk, "sphere_points_per_grid": nsph,
+                   "points_per_grid": n ** 3},
+        "algorithmic_bytes": {"pruned_step": total, "dense_step": 4 * 4.0 * 8 * n ** 3 * B,
+                              "per_pass": pass_bytes},
+        "hbm_gbs_algorithmic": round(total / (pruned_ms * 1e-3) / 1e9, 1),
+        "vs_dense_plans": equal,
+        "rel_l2_vs_fp64": dict(worst, sampled=[0, B - 1]),
+        "plans": {k: v.describe() for k, v in plans.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("pruned128", ("k_plane_pruned", "k_axis_str_pruned")[dom]),
-                     "kernel": ("k_plane_pruned<128,1>", "k_axis_str<128,1,64,false,true>")[dom],
-                     "ms_per_launch": round(pass_ms[dom], 5)},
+                     "traffic": measured_traffic("pruned128", kern[dom]),
+                     "kernel": kern[dom], "pass": dom, "ms_per_launch": round(times[dom], 5)},
         "cpu_baseline": None if args.no_cpu_baseline else _cpu_oracle(x, n, 1, args.cpu_seconds, "128^3 grids"),
         "source_hash": source_hash(),
     })

@@ -121,25 +121,37 @@ size_t fft3d_buffer_bytes(fft3d_plan_t plan);
 int fft3d_plan_describe(fft3d_plan_t plan, char *buf, size_t len);
 
 /*
- * Pruned inverse for sphere-cutoff input.  In a plane-wave code the
- * coefficients that feed the inverse transform of Eq. (1) (Section I: the
- * 3D FFTs that evaluate the quantum-mechanical operators, and the cutoff
- * restriction of the evaluation in Section III) vanish outside a sphere in
- * frequency space.  With the signed frequency G_d = k_d for k_d < N_d/2 and
- * k_d - N_d otherwise, the caller promises that every input point with
- * Gx^2 + Gy^2 + Gz^2 >= r2 is zero (their contents are never read).  The
- * plan then transforms only the xy-planes with Gz^2 < r2, reads in each only
- * the x-rows with Gy^2 + Gz^2 < r2, and its z pass skips the loads of the
- * other planes.  The result equals, bit for bit, the dense transform of the
- * same (zero-outside) input.  Applies to fft3d_exec and fft3d_exec_pass
- * (the pass list changes: the plane pass covers only those planes, and in
- * out-of-place use the intermediate planes outside the sphere are left
- * unwritten); the energy entry points are not affected.
+ * Pruned transforms for a sphere cutoff in frequency space.  In a plane-wave
+ * code the coefficients that enter the inverse transform of Eq. (1), and the
+ * ones kept after the forward transform, are those inside a sphere (the 3D
+ * FFTs that evaluate the quantum-mechanical operators, Section I, and the
+ * cutoff restriction of the evaluation in Section III).  With the signed
+ * frequency G_d = k_d for k_d < N_d/2 and k_d - N_d otherwise, the sphere is
+ * Gx^2 + Gy^2 + Gz^2 < r2.
+ *   INVERSE plan: the caller promises that every input point outside the
+ *     sphere is zero (those points are never read).  The plane pass handles
+ *     only the xy-planes with Gz^2 < r2 and reads in each only the x-rows
+ *     with Gy^2 + Gz^2 < r2; the z pass skips the loads of the other planes.
+ *     The result is the dense transform of the same input, computed by the
+ *     same butterflies in the same order.
+ *   FORWARD plan: only the output inside the sphere is wanted.  The plane
+ *     pass transforms every plane but stores only the points with
+ *     Gx^2 + Gy^2 < r2 (the z-lines the sphere meets); the z pass transforms
+ *     only those lines and stores only the points inside the sphere, which
+ *     hold the dense transform's values; all other output points are left
+ *     unspecified (they may hold intermediate values).
+ *   Both use the dense schedule's butterflies in the dense order; the
+ *   compiler may contract a few multiply-adds of the pruned kernels into
+ *   FMAs differently, so results agree with the dense plan's to FP32
+ *   rounding (in practice the inverse reproduces them bit for bit).
+ * Applies to fft3d_exec and fft3d_exec_pass (the pass list keeps its two
+ * passes, plane then z, with pruned kernels); the energy entry points are
+ * not affected.
  *   r2 > 0   set the cutoff (replacing an earlier one); r2 <= 0 clears it.
- * Returns FFT3D_E_UNSUPPORTED unless the plan is an FP32 INVERSE plan with
- * nx == ny from fft3d_plan; FFT3D_E_INVALID_ARG for NULL or NaN;
- * FFT3D_E_ALLOC if the plane list cannot be allocated (the plan is then
- * unchanged).  Not thread-safe against a concurrent exec of the same plan.
+ * Returns FFT3D_E_UNSUPPORTED unless the plan is an FP32 plan with nx == ny
+ * from fft3d_plan; FFT3D_E_INVALID_ARG for NULL or NaN; FFT3D_E_ALLOC if the
+ * plane list cannot be allocated (the plan is then unchanged).  Not
+ * thread-safe against a concurrent exec of the same plan.
  */
 int fft3d_plan_set_cutoff(fft3d_plan_t plan, double r2);
 

@@ -477,8 +477,7 @@ int fft3d_plan_set_cutoff(fft3d_plan_t p, double r2)
 {
     if (!p) return FFT3D_E_INVALID_ARG;
     if (!(r2 == r2)) return FFT3D_E_INVALID_ARG;   // NaN
-    if (p->many || p->precision != FFT3D_FP32 || p->direction != FFT3D_INVERSE || p->nx != p->ny)
-        return FFT3D_E_UNSUPPORTED;
+    if (p->many || p->precision != FFT3D_FP32 || p->nx != p->ny) return FFT3D_E_UNSUPPORTED;
     const int nx = p->nx, nz = p->nz;
     if (!plane_pruned_fn(nx, p->direction) || !axis_str_pruned_fn(nz, p->direction)) return FFT3D_E_UNSUPPORTED;
     if (p->dense_passes.empty()) p->dense_passes = p->passes;
@@ -514,9 +513,11 @@ int fft3d_plan_set_cutoff(fft3d_plan_t p, double r2)
         (void)hipGetLastError();
         cus = 1;
     }
-    const long planes = (long)p->batch * p->n_zlist;
-    const long resident = (long)plane_pf_blocks_per_cu(nx) * cus;
     const long B = p->batch;
+    const bool inv = p->direction == FFT3D_INVERSE;
+    // inverse: only the non-zero planes; forward: every plane
+    const long planes = inv ? B * p->n_zlist : B * nz;
+    const long resident = (long)plane_pf_blocks_per_cu(nx) * cus;
     const AxisMap zmap{B * p->ny * nx, nx, p->ny, p->vol, (long)nx, (long)nx * p->ny};
     p->passes.clear();
     p->passes.push_back({Pass::kPlanePrunedK, nx, planes, {}, p->tw_x, (int)(planes < resident ? planes : resident)});

@@ -47,7 +47,8 @@ static hipError_t launch_axis_str_pruned(const float2* in, float2* out, const fl
                                          hipStream_t st)
 {
     const long blocks = axis_str_blocks(m.lines);
-    hipLaunchKernelGGL((k_axis_str<N, S, kAxisLines, false, true>), dim3((unsigned)blocks),
+    // inverse plans prune the loads (sphere-limited input), forward plans lines and stores
+    hipLaunchKernelGGL((k_axis_str<N, S, kAxisLines, false, (S > 0 ? 1 : 2)>), dim3((unsigned)blocks),
                        dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, out, tw, m, nullptr, nullptr, 0L, R2);
     return hipGetLastError();
 }

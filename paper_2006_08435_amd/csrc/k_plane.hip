@@ -63,7 +63,8 @@ template <int N, int S>
 static hipError_t launch_plane_pruned(const float2* in, float2* out, const float2* tw, long planes, int grid,
                                       const int* zlist, int nzp, int nz, double R2, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_plane_pruned<N, S>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out, tw, planes,
+    // inverse plans prune planes and row loads, forward plans the stores
+    hipLaunchKernelGGL((k_plane_pruned<N, S, (S < 0)>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out, tw, planes,
                        zlist, nzp, nz, R2);
     return hipGetLastError();
 }

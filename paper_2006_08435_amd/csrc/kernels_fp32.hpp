@@ -381,12 +381,31 @@ k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long pl
 // Signed frequency of index k on a length-n axis (k for k < n/2, k - n above).
 __host__ __device__ __forceinline__ int signed_freq(int k, int n) { return 2 * k < n ? k : k - n; }
 
-// Pass A of the pruned inverse: the input vanishes outside the sphere
-// |G|^2 < R2 (G = signed frequencies).  Grids are [batch][nz][N][N]; only the
-// planes kz of zlist (those with Gz^2 < R2, nzp of them) are transformed, and in each only the rows with
-// Gy^2 + Gz^2 < R2 are read; the other rows of a plane are zeros.  Planes
-// outside zlist are neither read nor written (pass B treats them as zeros).
-template <int N, int S>
+// Plane output that stores only the points with Gx^2 + Gy^2 < R2.
+template <int N>
+struct PlaneColOutDisk {
+    float2* p;
+    double R2;
+    __device__ __forceinline__ float2 load(int, int) const { return float2{}; }
+    __device__ __forceinline__ void store(int x, int y, float2 v) const
+    {
+        const int gx = signed_freq(x, N), gy = signed_freq(y, N);
+        if ((double)(gx * gx + gy * gy) < R2) p[y * N + x] = v;
+    }
+};
+
+// The xy-plane pass of a pruned transform with the sphere |G|^2 < R2
+// (G = signed frequencies) on grids [batch][nz][N][N].
+//   OUT = false (inverse, input vanishing outside the sphere): only the
+//     planes kz of zlist (those with Gz^2 < R2, nzp of them; `planes` =
+//     batch * nzp) are transformed, and in each only the rows with
+//     Gy^2 + Gz^2 < R2 are read, the other rows being zeros.  Whole planes
+//     are written; the other planes are neither read nor written.
+//   OUT = true (forward, output wanted inside the sphere only): every plane
+//     (`planes` = batch * nz, zlist unused) is read whole and transformed;
+//     only the points with Gx^2 + Gy^2 < R2, the z-lines the sphere meets,
+//     are written.
+template <int N, int S, bool OUT>
 __global__ void __launch_bounds__(PlaneGeom<N>::T)
 k_plane_pruned(const float2* in, float2* out, const float2* __restrict__ tw, long planes, const int* __restrict__ zlist,
                int nzp, int nz, double R2)
@@ -396,27 +415,37 @@ k_plane_pruned(const float2* in, float2* out, const float2* __restrict__ tw, lon
     const int tid = threadIdx.x;
     TileRegs<N, N, T> regs;
     auto plane_base = [&](long i) {
+        if constexpr (OUT) return i * N * N;
         const long b = i / nzp;
         return (b * nz + zlist[i % nzp]) * (long)N * N;
     };
-    auto rows_of = [&](long i) {
-        const int gz = signed_freq(zlist[i % nzp], nz);
-        return [gz, R2](int y) {
-            const int gy = signed_freq(y, N);
-            return (double)(gy * gy + gz * gz) < R2;
-        };
+    auto load = [&](long i) {
+        if constexpr (OUT) {
+            regs.load(in + plane_base(i), tid);
+        } else {
+            const int gz = signed_freq(zlist[i % nzp], nz), gz2 = gz * gz;
+            regs.load_rows(in + plane_base(i), tid, [gz2, R2](int y) {
+                const int gy = signed_freq(y, N);
+                return (double)(gy * gy + gz2) < R2;
+            });
+        }
     };
     long p = blockIdx.x;
-    if (p < planes) regs.load_rows(in + plane_base(p), tid, rows_of(p));
+    if (p < planes) load(p);
     for (; p < planes; p += gridDim.x) {
         regs.template store_lds<RS>(lds, tid);
         __syncthreads();
         const long pn = p + gridDim.x;
-        if (pn < planes) regs.load_rows(in + plane_base(pn), tid, rows_of(pn));
+        if (pn < planes) load(pn);
         fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
         const LdsAcc<1, RS> col{lds};
-        const PlaneColOut<N> dst{out + plane_base(p)};
-        run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
+        if constexpr (OUT) {
+            const PlaneColOutDisk<N> dst{out + plane_base(p), R2};
+            run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
+        } else {
+            const PlaneColOut<N> dst{out + plane_base(p)};
+            run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
+        }
         __syncthreads();
     }
 }
@@ -708,29 +737,48 @@ __device__ __forceinline__ double block_sum(double x, double* red, int tid)
     return t;
 }
 
-// Strided global access whose element e reads as zero unless its signed
-// frequency satisfies G^2 < R2 (the z pass of the pruned inverse: planes
-// outside the sphere's z-range were never written by pass A).
+// Strided access of one z-line of a pruned transform with the sphere
+// |G|^2 < R2; gxy2 = Gx^2 + Gy^2 of the line, e the z index.
+// MODE 1 (z pass of the pruned inverse): loads of elements with
+//   Gz^2 >= R2 read zeros (those planes were never written by the plane
+//   pass); every element is stored.
+// MODE 2 (z pass of the pruned forward): a line with gxy2 >= R2 loads zeros
+//   (the plane pass did not write it) and every element outside the sphere
+//   is left unstored.
+template <int MODE>
 struct GlobStridedPruned {
     const float2* src;
     float2* dst;
     long es;
     int n;
+    int gxy2;
     double R2;
     __device__ __forceinline__ float2 load(int, int e) const
     {
-        const int g = signed_freq(e, n);
-        return (double)(g * g) < R2 ? src[(long)e * es] : make_float2(0.f, 0.f);
+        if constexpr (MODE == 1) {
+            const int g = signed_freq(e, n);
+            return (double)(g * g) < R2 ? src[(long)e * es] : make_float2(0.f, 0.f);
+        } else {
+            return (double)gxy2 < R2 ? src[(long)e * es] : make_float2(0.f, 0.f);
+        }
     }
-    __device__ __forceinline__ void store(int, int e, float2 v) const { dst[(long)e * es] = v; }
+    __device__ __forceinline__ void store(int, int e, float2 v) const
+    {
+        if constexpr (MODE == 2) {
+            const int g = signed_freq(e, n);
+            if ((double)(gxy2 + g * g) < R2) dst[(long)e * es] = v;
+        } else {
+            dst[(long)e * es] = v;
+        }
+    }
 };
 
 // ENERGY: the pass is the last one of an inverse transform psi = IFFT(c);
 // while storing psi it accumulates sum V |psi|^2 and writes one FP64 partial
 // per workgroup to partials[blockIdx.x] (V indexed by position in the grid).
-// PRUNE (z pass of the pruned inverse): stage-0 loads of elements whose
-// signed frequency has G^2 >= R2 are skipped (zeros).
-template <int N, int S, int L, bool ENERGY = false, bool PRUNE = false>
+// PRUNE: 0 dense; 1 z pass of the pruned inverse, 2 z pass of the pruned
+// forward (GlobStridedPruned; both require the z-pass AxisMap).
+template <int N, int S, int L, bool ENERGY = false, int PRUNE = 0>
 __global__ void __launch_bounds__((AxisGeom<N, L>::T))
 k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap m, const float* __restrict__ V,
            double* __restrict__ partials, long vol, double R2 = 0.0)
@@ -765,15 +813,22 @@ k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap
         }
         const double t = block_sum<T>(eg.acc, red, tid);
         if (tid == 0) partials[blockIdx.x] = t;
-    } else if constexpr (PRUNE) {
-        const GlobStridedPruned gp{in + gbase, out + gbase, m.es, N, R2};
+    } else if constexpr (PRUNE != 0) {
+        int gxy2 = 0;
+        if constexpr (PRUNE == 2) {   // z pass: line li = (b * ny + y) * nx + x with odiv = ny
+            const long o = li / m.nx;
+            const int gx = signed_freq((int)(li - o * m.nx), (int)m.nx);
+            const int gy = signed_freq((int)(o % m.odiv), (int)m.odiv);
+            gxy2 = gx * gx + gy * gy;
+        }
+        const GlobStridedPruned<PRUNE> gp{in + gbase, out + gbase, m.es, N, gxy2, R2};
         if constexpr (P::stages == 1) {
-            fft_stage<N, 0, S, L, T, true, false>(gp, g, tw, tid, valid);
+            fft_stage<N, 0, S, L, T, true, false>(gp, gp, tw, tid, valid);
         } else {
             const LdsAcc<1, G::LP> a{lds};
             fft_stage<N, 0, S, L, T, true, false>(gp, a, tw, tid, valid);
             __syncthreads();
-            run_tail<N, S, L, T, 1, false>(a, g, tw, tid, valid);
+            run_tail<N, S, L, T, 1, false>(a, gp, tw, tid, valid);
         }
     } else {
         if constexpr (P::stages == 1) {

@@ -34,9 +34,13 @@ long axis_str_blocks(long lines);
 hipError_t launch_sum_partials(const double* partials, long n, double* out, hipStream_t st);
 PlaneFn plane_fn(int n, int sign);
 PlanePfFn plane_pf_fn(int n, int sign);
-// Pruned inverse (input vanishing outside |G|^2 < R2): pass A over the
-// planes of zlist only, reading only rows inside the sphere; pass B with
-// zero loads for planes outside it.
+// Pruned transforms for the sphere |G|^2 < R2 (signed frequencies), both in
+// the dense order (xy planes, then z).  Inverse (sign +1, input vanishing
+// outside the sphere): plane pass over the planes of zlist reading only rows
+// inside the sphere, then the z pass with zero loads for the other planes.
+// Forward (sign -1, output wanted inside the sphere only): plane pass over
+// every plane storing only the z-lines the sphere meets, then the z pass
+// over those lines storing only the sphere.
 using PlanePrunedFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, int grid,
                                      const int* zlist, int nzp, int nz, double R2, hipStream_t st);
 using AxisStrPrunedFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, const AxisMap& m, double R2,
