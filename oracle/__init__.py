@@ -81,6 +81,8 @@ def _bind(lib):
     lib.oracle_q16_encode.argtypes = [ci, ctypes.c_long, ci, fp, u16, i8]
     lib.oracle_q16_decode.argtypes = [ci, ctypes.c_long, ci, u16, i8, dp]
     lib.oracle_energy.argtypes = [ci, ci, ci, ci, dp, dp, dp, dp, dp]
+    lib.oracle_r2c3d.argtypes = [ci, ci, ci, ci, dp, dp]
+    lib.oracle_c2r3d.argtypes = [ci, ci, ci, ci, dp, dp]
     return lib
 
 
@@ -172,6 +174,34 @@ def fft3d(a, sign: int = -1, order=(0, 1, 2)) -> np.ndarray:
     o = (ctypes.c_int * 3)(*[int(v) for v in order])
     _check(lib.oracle_fft3d_order(nx, ny, nz, b, int(sign),
                                   _ptr(x, ctypes.c_double), _ptr(out, ctypes.c_double), o))
+    return out[0] if squeeze else out
+
+
+def r2c3d(f) -> np.ndarray:
+    """Half spectrum [.., z, y, x/2+1] of a real grid [.., z, y, x] (x even)."""
+    lib = _load()
+    x = np.ascontiguousarray(f, dtype=np.float64)
+    squeeze = x.ndim == 3
+    if squeeze:
+        x = x[None]
+    b, nz, ny, nx = x.shape
+    out = np.empty((b, nz, ny, nx // 2 + 1), np.complex128)
+    _check(lib.oracle_r2c3d(nx, ny, nz, b, _ptr(x, ctypes.c_double), _ptr(out, ctypes.c_double)))
+    return out[0] if squeeze else out
+
+
+def c2r3d(h, nx: int) -> np.ndarray:
+    """Unnormalised real inverse of a half spectrum [.., z, y, nx/2+1]."""
+    lib = _load()
+    x = np.ascontiguousarray(h, dtype=np.complex128)
+    squeeze = x.ndim == 3
+    if squeeze:
+        x = x[None]
+    b, nz, ny, hh = x.shape
+    if hh != nx // 2 + 1:
+        raise ValueError("half spectrum width %d does not match nx=%d" % (hh, nx))
+    out = np.empty((b, nz, ny, nx), np.float64)
+    _check(lib.oracle_c2r3d(nx, ny, nz, b, _ptr(x, ctypes.c_double), _ptr(out, ctypes.c_double)))
     return out[0] if squeeze else out
 
 

@@ -25,8 +25,9 @@
  * in double on an index already reduced modulo N, so no large argument ever
  * reaches cos/sin.
  *
- * The scaled 16-bit storage format and the plane-wave local-potential energy
- * are the two other forms this project builds on top of the transform; they
+ * Real-grid transforms (r2c / c2r), the scaled 16-bit storage format and the
+ * plane-wave local-potential energy are the other forms this project builds
+ * on top of the transform; they
  * are defined here from their plain definitions (see the comments on each
  * function).  All rounding to 16-bit formats is written out from the IEEE
  * definitions of binary16 and bfloat16 (round to nearest, ties to even).
@@ -257,6 +258,82 @@ int oracle_fft3d(int nx, int ny, int nz, int batch, int sign,
 {
     static const int xyz[3] = {0, 1, 2};
     return oracle_fft3d_order(nx, ny, nz, batch, sign, in, out, xyz);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Real grids (densities and potentials are real)                            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * r2c: Eq. (1) of a real grid f (imaginary parts zero), sign -1, keeping the
+ * half kx = 0 .. nx/2 of the x frequencies; the other half follows from
+ * F(-k) = conj F(k).  in: real [batch][z][y][x]; out: complex
+ * [batch][z][y][nx/2 + 1].  nx must be even.
+ */
+int oracle_r2c3d(int nx, int ny, int nz, int batch, const double *in, double *out)
+{
+    if (nx < 2 || nx % 2 || ny < 1 || nz < 1 || batch < 1) return -1;
+    const long vol = (long)nx * ny * nz, rows = (long)ny * nz * batch;
+    const int h = nx / 2 + 1;
+    double *full = malloc(sizeof(double) * 2 * vol * batch);
+    if (!full) return -4;
+    for (long i = 0; i < vol * batch; ++i) {
+        full[2 * i] = in[i];
+        full[2 * i + 1] = 0.0;
+    }
+    int err = oracle_fft3d(nx, ny, nz, batch, -1, full, full);
+    if (!err)
+        for (long r = 0; r < rows; ++r)
+            for (int k = 0; k < h; ++k) {
+                out[2 * (r * h + k)] = full[2 * (r * nx + k)];
+                out[2 * (r * h + k) + 1] = full[2 * (r * nx + k) + 1];
+            }
+    free(full);
+    return err;
+}
+
+/*
+ * c2r: the unnormalised inverse of a half spectrum H [batch][z][y][nx/2 + 1]
+ * (the inverse of its Hermitian extension, the sign +1 form of Eq. (1)):
+ * complex inverse transforms along z and y, then along x the real sum
+ *   f(x) = Re H_0 + (-1)^x Re H_{nx/2}
+ *          + 2 sum_{0 < k < nx/2} (Re H_k cos(2 pi k x / nx) - Im H_k sin(2 pi k x / nx)),
+ * so the imaginary parts of the kx = 0 and kx = nx/2 entries do not
+ * contribute.  out: real [batch][z][y][x].  nx must be even.
+ */
+int oracle_c2r3d(int nx, int ny, int nz, int batch, const double *in, double *out)
+{
+    if (nx < 2 || nx % 2 || ny < 1 || nz < 1 || batch < 1) return -1;
+    const int h = nx / 2 + 1;
+    const long hvol = (long)h * ny * nz, rows = (long)ny * nz * batch;
+    double *t = malloc(sizeof(double) * 2 * hvol * batch);
+    double *w = malloc(sizeof(double) * 2 * nx);
+    if (!t || !w) {
+        free(t);
+        free(w);
+        return -4;
+    }
+    memcpy(t, in, sizeof(double) * 2 * hvol * batch);
+    int err = axis_pass(h, ny, nz, batch, +1, 1, t);
+    if (!err) err = axis_pass(h, ny, nz, batch, +1, 2, t);
+    if (!err) {
+        root_table(nx, +1, w);
+#pragma omp parallel for schedule(static)
+        for (long r = 0; r < rows; ++r) {
+            const double *H = t + 2 * r * h;
+            for (int x = 0; x < nx; ++x) {
+                double v = H[0] + ((x & 1) ? -H[2 * (nx / 2)] : H[2 * (nx / 2)]);
+                for (int k = 1; k < nx / 2; ++k) {
+                    const long e = ((long)k * x) % nx;
+                    v += 2.0 * (H[2 * k] * w[2 * e] - H[2 * k + 1] * w[2 * e + 1]);
+                }
+                out[r * nx + x] = v;
+            }
+        }
+    }
+    free(t);
+    free(w);
+    return err;
 }
 
 void oracle_set_threads(int n)

@@ -12,8 +12,9 @@ Sources of truth (none of them is the oracle itself):
 * invariants: forward(inverse) = N^3 I, Parseval, linearity, shift theorem,
   Hermitian symmetry of the transform of real data, separability (any axis
   order gives the same result);
-* independent library routines as witnesses: numpy.fft (pocketfft), numpy's
-  float16 conversion, torch's bfloat16 conversion, torch autograd.
+* independent library routines as witnesses: numpy.fft (pocketfft, also its
+  real transforms rfftn / irfftn), numpy's float16 conversion, torch's
+  bfloat16 conversion, torch autograd.
 """
 from __future__ import annotations
 
@@ -274,6 +275,38 @@ def pin_energy():
     assert rel(grad, ct.grad.numpy()) < 1e-12
 
 
+# ------------------------------------------------------------ real grids ----
+
+REAL_SHAPES = [(8, 6, 5), (2, 3, 4), (12, 12, 5), (10, 1, 3), (6, 4, 1)]   # (nx, ny, nz)
+
+
+def pin_real():
+    """r2c / c2r: numpy's rfftn / irfftn as witnesses, a plane-wave closed
+    form, and the round trip c2r(r2c(f)) = NxNyNz f."""
+    for i, (nx, ny, nz) in enumerate(REAL_SHAPES):
+        vol = nx * ny * nz
+        f = np.random.default_rng(300 + i).standard_normal((2, nz, ny, nx))
+        H = oracle.r2c3d(f)
+        assert H.shape == (2, nz, ny, nx // 2 + 1)
+        assert rel(H, np.fft.rfftn(f, axes=(-3, -2, -1))) < 1e-13, (nx, ny, nz)
+        back = oracle.c2r3d(H, nx)
+        assert np.max(np.abs(back - vol * f)) < 1e-12 * vol * np.max(np.abs(f)), (nx, ny, nz)
+        # an arbitrary (not Hermitian) half spectrum: the imaginary parts of
+        # the kx = 0 and kx = nx/2 entries must not contribute
+        h = rand_grid((2, nz, ny, nx // 2 + 1), 400 + i)
+        want = np.fft.irfftn(h, s=(nz, ny, nx), axes=(-3, -2, -1)) * vol
+        got = oracle.c2r3d(h, nx)
+        assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want)), (nx, ny, nz)
+    # plane wave cos(2 pi (a x/nx + b y/ny + c z/nz)): half spectrum vol/2 at (c, b, a)
+    nx, ny, nz, a, b, c = 12, 10, 6, 5, 3, 4
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    f = np.cos(2 * np.pi * (a * x / nx + b * y / ny + c * z / nz))
+    H = oracle.r2c3d(f)
+    want = np.zeros((nz, ny, nx // 2 + 1), np.complex128)
+    want[c, b, a] = nx * ny * nz / 2
+    assert np.max(np.abs(H - want)) < 1e-10
+
+
 ALL_PINS = [pin_golden, pin_closed_forms, pin_naive_vs_numpy, pin_fft_vs_naive,
             pin_fft_vs_numpy, pin_invariants, pin_fp16_rounding, pin_bf16_rounding,
-            pin_q16_rule, pin_energy]
+            pin_q16_rule, pin_energy, pin_real]

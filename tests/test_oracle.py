@@ -59,3 +59,7 @@ def test_rejects_bad_arguments():
         oracle.fft3d(np.zeros((2, 2, 2), complex), sign=0)
     with pytest.raises(RuntimeError):
         oracle.fft3d(np.zeros((2, 2, 2), complex), order=(0, 0, 1))
+
+
+def test_real_transforms():
+    P.pin_real()

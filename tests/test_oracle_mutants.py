@@ -31,6 +31,12 @@ MUTANTS = {
     "exponent off by one": ("e = ilogb(m) - 14;", "e = ilogb(m) - 15;"),
     "ties round up": ("return fmod(f, 2.0) == 0.0 ? f : f + 1.0;", "return f + 1.0;"),
     "no subnormal quantum": ("if (e < emin) e = emin;", "(void)emin;"),
+    "c2r drops factor 2": ("v += 2.0 * (H[2 * k]", "v += (H[2 * k]"),
+    "c2r Nyquist sign": ("((x & 1) ? -H[2 * (nx / 2)] : H[2 * (nx / 2)])", "H[2 * (nx / 2)]"),
+    "c2r sin sign": ("- H[2 * k + 1] * w[2 * e + 1]", "+ H[2 * k + 1] * w[2 * e + 1]"),
+    "c2r skips z": ("if (!err) err = axis_pass(h, ny, nz, batch, +1, 2, t);", "(void)0;"),
+    "r2c wrong half": ("out[2 * (r * h + k)] = full[2 * (r * nx + k)];",
+                       "out[2 * (r * h + k)] = full[2 * (r * nx + (nx - k) % nx)];"),
 }
 
 
