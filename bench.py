@@ -33,7 +33,7 @@ WORKLOADS = {
     "single64": (64, 1, 2064, "c2c 3D FFT, one 64^3 grid, inverse then forward, complex64"),
     "batch64": (64, 256, 4000, "c2c 3D FFT, 256 grids of 64^3, inverse then forward, complex64"),
 }
-EXTRA_WORKLOADS = ("mixed", "energy96", "fp16_128", "bf16_128", "pruned128")
+EXTRA_WORKLOADS = ("mixed", "energy96", "fp16_128", "bf16_128", "pruned128", "real128")
 
 
 def source_hash() -> str:
@@ -97,6 +97,8 @@ def main(argv=None):
         return bench_energy(args)
     if args.workload == "pruned128":
         return bench_pruned(args)
+    if args.workload == "real128":
+        return bench_real(args)
     if args.workload in ("fp16_128", "bf16_128"):
         return bench_q16(args, args.workload[:4])
     n, batch, seed0, desc = WORKLOADS[args.workload]
@@ -421,8 +423,18 @@ def bench_pruned(args):
         plans["dense_inverse"].exec_ptr(xt.data_ptr(), d_psi.data_ptr(), sh)
         plans["dense_forward"].exec_ptr(d_psi.data_ptr(), d_back.data_ptr(), sh)
 
+    npts = plans["inverse"].sphere_points
+    packed_c = plans["inverse"].pack(xt)
+    packed_back = torch.empty_like(packed_c)
+    work = torch.empty_like(xt)
+
+    def packed_step():
+        _lib.check(L.fft3d_exec_packed(plans["inverse"].handle, work.data_ptr(), packed_c.data_ptr(), sh))
+        _lib.check(L.fft3d_exec_packed(plans["forward"].handle, work.data_ptr(), packed_back.data_ptr(), sh))
+
     pruned_ms = _time(pruned_step, args.steps, args.warmup, stream)
     dense_ms = _time(dense_step, args.steps, args.warmup, stream)
+    packed_ms = _time(packed_step, args.steps, args.warmup, stream)
     times = {}
     for name, src, dst in (("inverse", xt, psi), ("forward", psi, back)):
         pl = plans[name]
@@ -437,7 +449,9 @@ def bench_pruned(args):
                 args.steps, args.warmup, stream)
     pruned_step()
     dense_step()
+    packed_step()
     torch.cuda.synchronize()
+    packed_rt = float(((packed_back / n ** 3) - packed_c).abs().max() / packed_c.abs().max())
     g = workloads.signed_freq(n)
     sphere = (g[:, None, None] ** 2 + g[None, :, None] ** 2 + g[None, None, :] ** 2) < r2
     ms = torch.from_numpy(np.broadcast_to(sphere[None], x.shape).copy()).cuda()
@@ -475,14 +489,16 @@ def bench_pruned(args):
             "forward_pass0": "k_plane_pruned<128,-1,true>", "forward_pass1": "k_axis_str<128,-1,64,false,2>"}
     rec.update({
         "times_ms": dict({"pruned_step": round(pruned_ms, 4), "dense_step": round(dense_ms, 4),
-                          "speedup": round(dense_ms / pruned_ms, 3)},
+                          "speedup": round(dense_ms / pruned_ms, 3),
+                          "packed_step": round(packed_ms, 4)},
                          **{k: round(v, 4) for k, v in times.items()}),
         "sphere": {"nonzero_planes": nzp, "disk_lines_per_grid": disk, "sphere_points_per_grid": nsph,
                    "points_per_grid": n ** 3},
-        "algorithmic_bytes": {"pruned_step": total, "dense_step": 4 * 4.0 * 8 * n ** 3 * B,
+        "algorithmic_bytes": {"pruned_step": total, "dense_step": 2 * 2 * 2 * 8.0 * n ** 3 * B,
                               "per_pass": pass_bytes},
         "hbm_gbs_algorithmic": round(total / (pruned_ms * 1e-3) / 1e9, 1),
         "vs_dense_plans": equal,
+        "packed": {"points_per_grid": npts, "round_trip_max_abs_err_over_max": packed_rt},
         "rel_l2_vs_fp64": dict(worst, sampled=[0, B - 1]),
         "plans": {k: v.describe() for k, v in plans.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -490,6 +506,84 @@ def bench_pruned(args):
                      "traffic": measured_traffic("pruned128", kern[dom]),
                      "kernel": kern[dom], "pass": dom, "ms_per_launch": round(times[dom], 5)},
         "cpu_baseline": None if args.no_cpu_baseline else _cpu_oracle(x, n, 1, args.cpu_seconds, "128^3 grids"),
+        "source_hash": source_hash(),
+    })
+    print(json.dumps(rec))
+    return 0
+
+
+def bench_real(args):
+    """32 real grids of 128^3: r2c then c2r (the c2r consumes, and
+    overwrites, the r2c's half spectrum)."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2006_08435_amd as fft3d
+    from paper_2006_08435_amd import _lib
+    n, B = 128, 32
+    h = n // 2 + 1
+    f = np.random.default_rng(9900).uniform(-1, 1, (B, n, n, n)).astype(np.float32)
+    ft = torch.from_numpy(f).cuda()
+    half = torch.empty((B, n, n, h), dtype=torch.complex64, device="cuda")
+    back = torch.empty_like(ft)
+    fwd = fft3d.RealPlan(n, n, n, B, fft3d.FFT3D_FORWARD)
+    inv = fft3d.RealPlan(n, n, n, B, fft3d.FFT3D_INVERSE)
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    L = _lib.lib()
+
+    def step():
+        _lib.check(L.fft3d_exec(fwd.handle, ft.data_ptr(), half.data_ptr(), sh))
+        _lib.check(L.fft3d_exec(inv.handle, half.data_ptr(), back.data_ptr(), sh))
+
+    ms = _time(step, args.steps, args.warmup, stream)
+    times = {}
+    # (buffers per pass: r2c = [plane ft -> half, z in place on half];
+    #  c2r = [z in place on half, plane half -> back])
+    for name, pl, bufs in (("r2c", fwd, ((ft, half), (half, half))), ("c2r", inv, ((half, half), (half, back)))):
+        for k in range(L.fft3d_plan_passes(pl.handle)):
+            a_, b_ = bufs[k]
+            times["%s_pass%d" % (name, k)] = _time(
+                lambda: _lib.check(L.fft3d_exec_pass(pl.handle, k, a_.data_ptr(), b_.data_ptr(), sh)),
+                args.steps, args.warmup, stream)
+    # the timing loop above left `half` transformed in place: recompute and check
+    _lib.check(L.fft3d_exec(fwd.handle, ft.data_ptr(), half.data_ptr(), sh))
+    torch.cuda.synchronize()
+    H = half.cpu().numpy()
+    worst = {"r2c": 0.0, "round_trip": 0.0}
+    for j in (0, B - 1):
+        ref = oracle.r2c3d(f[j].astype(np.float64))
+        worst["r2c"] = max(worst["r2c"], float(np.linalg.norm(H[j] - ref) / np.linalg.norm(ref)))
+    _lib.check(L.fft3d_exec(inv.handle, half.data_ptr(), back.data_ptr(), sh))
+    torch.cuda.synchronize()
+    bk = back.cpu().numpy()
+    for j in (0, B - 1):
+        worst["round_trip"] = max(worst["round_trip"],
+                                  float(np.linalg.norm(bk[j] / n ** 3 - f[j]) / np.linalg.norm(f[j])))
+    real_b, half_b = 4.0 * n ** 3, 8.0 * n * n * h
+    pass_bytes = {"r2c_pass0": (real_b + half_b) * B, "r2c_pass1": 2 * half_b * B,
+                  "c2r_pass0": 2 * half_b * B, "c2r_pass1": (half_b + real_b) * B}
+    total = sum(pass_bytes.values())
+    flops = 2 * 2.5 * n ** 3 * math.log2(n ** 3) * B
+    rec = _base_record(flops / (ms * 1e-3) / 1e9, "GFLOP/s", args, ms,
+                       "real 3D FFT, 32 real grids of 128^3: r2c then c2r, float32 / complex64 half spectra; "
+                       "GFLOP/s counts 2.5 N^3 log2 N^3 per real transform",
+                       {"n": n, "batch": B, "precision": "fp32", "input": "uniform real grids"})
+    dom = max(pass_bytes, key=lambda k: times[k])
+    achieved = pass_bytes[dom] / (times[dom] * 1e-3) / 1e9
+    kern = {"r2c_pass0": "k_plane_r2c<128,-1>", "r2c_pass1": "k_axis_str<128,-1,64> (half layout)",
+            "c2r_pass0": "k_axis_str<128,1,64> (half layout)", "c2r_pass1": "k_plane_c2r<128,1>"}
+    rec.update({
+        "times_ms": {k: round(v, 4) for k, v in times.items()},
+        "algorithmic_bytes": dict({"step": total}, **pass_bytes),
+        "hbm_gbs_algorithmic": round(total / (ms * 1e-3) / 1e9, 1),
+        "hbm_frac_algorithmic": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "rel_l2_vs_fp64": dict(worst, sampled=[0, B - 1]),
+        "plans": {"r2c": fwd.describe(), "c2r": inv.describe()},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("real128", kern[dom]),
+                     "kernel": kern[dom], "pass": dom, "ms_per_launch": round(times[dom], 5)},
+        "cpu_baseline": None,
         "source_hash": source_hash(),
     })
     print(json.dumps(rec))

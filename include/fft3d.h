@@ -93,6 +93,33 @@ enum fft3d_status {
 fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int direction);
 
 /*
+ * Real grids.  Densities and potentials, the other grids a plane-wave code
+ * transforms (Section I), are real; their transform under Eq. (1) is
+ * Hermitian, F(-k) = conj F(k), so half of it is kept: kx = 0 .. nx/2.
+ * Plan `batch` real transforms with nx == ny, nx even (each dimension as in
+ * fft3d_plan), FP32.
+ *   FORWARD (r2c): in = real float32 [batch][nz][ny][nx], out = complex64
+ *     [batch][nz][ny][nx/2 + 1], the kx <= nx/2 half of Eq. (1).
+ *   INVERSE (c2r): in = complex64 [batch][nz][ny][nx/2 + 1], out = real
+ *     float32 [batch][nz][ny][nx]: the unnormalised inverse of the Hermitian
+ *     extension (complex inverse along z and y, then the real inverse along
+ *     x, which ignores the imaginary parts of the kx = 0 and kx = nx/2
+ *     entries); c2r(r2c(f)) = nx*ny*nz*f.  The input buffer is used as the
+ *     workspace of the z pass and is OVERWRITTEN.
+ * fft3d_exec(plan, in, out, stream) runs it; in and out must be distinct
+ * (FFT3D_E_INVALID_ARG otherwise).  fft3d_buffer_bytes returns the bytes of
+ * the complex side, fft3d_real_bytes those of the real side (0 for plans
+ * that are not real).  Passes (fft3d_exec_pass): r2c = [plane in -> out,
+ * z in place on out]; c2r = [z in place on `in`, plane in -> out].  The z
+ * pass always works in place on the complex-side buffer (out of an r2c, in
+ * of a c2r) whatever the other pointer is.
+ * Returns NULL with FFT3D_E_UNSUPPORTED for nx != ny or nx odd; other
+ * errors as fft3d_plan.  Energy and cutoff entry points reject real plans.
+ */
+fft3d_plan_t fft3d_plan_real(int nx, int ny, int nz, int batch, int direction);
+size_t fft3d_real_bytes(fft3d_plan_t plan);
+
+/*
  * Enqueue the transform of `in` into `out` on `stream`.  Both are device
  * buffers of fft3d_buffer_bytes(plan) bytes.  in == out (in place) is
  * allowed; out-of-place calls leave `in` unmodified.  Returns FFT3D_OK,
@@ -154,6 +181,37 @@ int fft3d_plan_describe(fft3d_plan_t plan, char *buf, size_t len);
  * thread-safe against a concurrent exec of the same plan.
  */
 int fft3d_plan_set_cutoff(fft3d_plan_t plan, double r2);
+
+/*
+ * Packed spheres.  Plane-wave codes keep only the coefficients inside the
+ * cutoff sphere.  The packed form of a plan with a cutoff (see above) lists,
+ * for each grid of the batch in turn, the points inside the sphere in the
+ * grid's own order (kz, then ky, then kx ascending): exactly the points
+ * dense[b][kz][ky][kx] with Gx^2 + Gy^2 + Gz^2 < r2, as a boolean-mask
+ * selection in row-major order would list them.  A packed buffer holds
+ * batch * fft3d_plan_sphere_points(plan) complex64 values, grid after grid.
+ *
+ * fft3d_plan_sphere_points: points per grid inside the sphere, or
+ *   FFT3D_E_INVALID_ARG (NULL) / FFT3D_E_UNSUPPORTED (no cutoff set).
+ * fft3d_sphere_pack: gather dense [batch][nz][ny][nx] -> packed.
+ * fft3d_sphere_unpack: scatter packed -> dense, writing zeros at every point
+ *   outside the sphere.
+ * fft3d_exec_packed: the pruned transform with the sphere in packed form.
+ *   INVERSE plan: reads `packed`, writes the dense result to `dense` (the
+ *     plane pass gathers its rows straight from the packed sphere); equal to
+ *     fft3d_exec on the unpacked input.
+ *   FORWARD plan: reads `dense`, which is also used as the workspace of the
+ *     first pass and is overwritten, and writes the points inside the
+ *     sphere to `packed` (the z pass scatters them there directly).
+ * All three copy/transform calls are enqueued on `stream`.  Pointers must be
+ * 16-byte aligned device pointers to distinct buffers.  Return FFT3D_OK,
+ * FFT3D_E_INVALID_ARG (NULL, or the same buffer twice), FFT3D_E_ALIGNMENT,
+ * FFT3D_E_UNSUPPORTED (no cutoff set) or FFT3D_E_LAUNCH.
+ */
+long long fft3d_plan_sphere_points(fft3d_plan_t plan);
+int fft3d_sphere_pack(fft3d_plan_t plan, const void *dense, void *packed, fft3d_stream_t stream);
+int fft3d_sphere_unpack(fft3d_plan_t plan, const void *packed, void *dense, fft3d_stream_t stream);
+int fft3d_exec_packed(fft3d_plan_t plan, void *dense, void *packed, fft3d_stream_t stream);
 
 /*
  * Measurement hooks.  An exec is a fixed sequence of kernel launches

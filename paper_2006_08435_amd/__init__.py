@@ -65,6 +65,54 @@ class Plan:
         restores the dense schedule (``fft3d_plan_set_cutoff``)."""
         _lib.check(_lib.lib().fft3d_plan_set_cutoff(self._h, float(r2)), "fft3d_plan_set_cutoff")
 
+    @property
+    def sphere_points(self) -> int:
+        """Points per grid inside the cutoff sphere (a cutoff must be set)."""
+        n = int(_lib.lib().fft3d_plan_sphere_points(self._h))
+        _lib.check(min(n, 0), "fft3d_plan_sphere_points")
+        return n
+
+    def _packed_like(self, dense):
+        torch = _torch()
+        return torch.empty((self.shape[0], self.sphere_points), dtype=dense.dtype, device=dense.device)
+
+    def _check_pair(self, dense, packed):
+        for t in (dense, packed):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("tensors must be contiguous device tensors")
+        if dense.numel() * dense.element_size() != self.buffer_bytes:
+            raise ValueError("dense tensor holds %d bytes, plan needs %d"
+                             % (dense.numel() * dense.element_size(), self.buffer_bytes))
+        if packed.numel() != self.shape[0] * self.sphere_points or packed.element_size() != 8:
+            raise ValueError("packed tensor must hold batch * sphere_points complex64 values")
+
+    def pack(self, dense, packed=None, stream=None):
+        """Gather the points inside the cutoff sphere: [batch, sphere_points]."""
+        if packed is None:
+            packed = self._packed_like(dense)
+        self._check_pair(dense, packed)
+        _lib.check(_lib.lib().fft3d_sphere_pack(self._h, dense.data_ptr(), packed.data_ptr(),
+                                                _stream_handle(stream)), "fft3d_sphere_pack")
+        return packed
+
+    def unpack(self, packed, dense=None, stream=None):
+        """Scatter a packed sphere into a dense grid (zeros outside)."""
+        torch = _torch()
+        if dense is None:
+            dense = torch.empty(self.shape, dtype=packed.dtype, device=packed.device)
+        self._check_pair(dense, packed)
+        _lib.check(_lib.lib().fft3d_sphere_unpack(self._h, packed.data_ptr(), dense.data_ptr(),
+                                                  _stream_handle(stream)), "fft3d_sphere_unpack")
+        return dense
+
+    def exec_packed(self, dense, packed, stream=None):
+        """Pruned transform with a packed sphere: inverse packed -> dense;
+        forward dense -> packed (``dense`` is overwritten as workspace)."""
+        self._check_pair(dense, packed)
+        _lib.check(_lib.lib().fft3d_exec_packed(self._h, dense.data_ptr(), packed.data_ptr(),
+                                                _stream_handle(stream)), "fft3d_exec_packed")
+        return dense if self.direction == FFT3D_INVERSE else packed
+
     def exec_ptr(self, in_ptr: int, out_ptr: int, stream_handle: int) -> None:
         _lib.check(_lib.lib().fft3d_exec(self._h, in_ptr, out_ptr, stream_handle), "fft3d_exec")
 
@@ -166,6 +214,74 @@ _cache = {}
 _cache_lock = threading.Lock()
 
 
+class RealPlan:
+    """Real grids (nx == ny, nx even): r2c forward real [B,Nz,Ny,Nx] ->
+    complex [B,Nz,Ny,Nx/2+1]; c2r inverse the reverse, unnormalised, with the
+    complex input overwritten (``fft3d_plan_real``)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, batch: int = 1, direction: int = FFT3D_FORWARD):
+        lib = _lib.lib()
+        h = lib.fft3d_plan_real(int(nx), int(ny), int(nz), int(batch), int(direction))
+        if not h:
+            raise Fft3dError(lib.fft3d_last_error(), "fft3d_plan_real(%d,%d,%d,%d)" % (nx, ny, nz, batch))
+        self._h = h
+        self.real_shape = (int(batch), int(nz), int(ny), int(nx))
+        self.half_shape = (int(batch), int(nz), int(ny), int(nx) // 2 + 1)
+        self.direction = int(direction)
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    def describe(self) -> str:
+        import ctypes
+        buf = ctypes.create_string_buffer(512)
+        _lib.lib().fft3d_plan_describe(self._h, buf, 512)
+        return buf.value.decode()
+
+    def exec(self, inp, out=None, stream=None):
+        torch = _torch()
+        fwd = self.direction == FFT3D_FORWARD
+        in_dtype, out_dtype = (torch.float32, torch.complex64) if fwd else (torch.complex64, torch.float32)
+        in_shape, out_shape = (self.real_shape, self.half_shape) if fwd else (self.half_shape, self.real_shape)
+        if out is None:
+            out = torch.empty(out_shape, dtype=out_dtype, device=inp.device)
+        for t, dt, sh in ((inp, in_dtype, in_shape), (out, out_dtype, out_shape)):
+            if not t.is_cuda or not t.is_contiguous() or t.dtype != dt or tuple(t.shape) != sh:
+                raise ValueError("expected a contiguous %s device tensor of shape %s" % (dt, sh))
+        _lib.check(_lib.lib().fft3d_exec(self._h, inp.data_ptr(), out.data_ptr(), _stream_handle(stream)),
+                   "fft3d_exec")
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.lib().fft3d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rfftn(x):
+    """Half spectrum (kx <= Nx/2) of real grids [B,Nz,Ny,Nx] or [Nz,Ny,Nx]."""
+    xb, sq = _as_batch(x)
+    b, nz, ny, nx = xb.shape
+    y = RealPlan(nx, ny, nz, b, FFT3D_FORWARD).exec(xb.contiguous())
+    return y[0] if sq else y
+
+
+def irfftn(h, nx: int):
+    """Unnormalised real inverse of half spectra [B,Nz,Ny,Nx/2+1] (the input
+    is copied first, since the transform overwrites its input)."""
+    hb, sq = _as_batch(h)
+    b, nz, ny, _ = hb.shape
+    y = RealPlan(nx, ny, nz, b, FFT3D_INVERSE).exec(hb.clone())
+    return y[0] if sq else y
+
+
 def get_plan(nx, ny, nz, batch=1, precision="fp32", direction=FFT3D_FORWARD) -> Plan:
     import torch
     key = (nx, ny, nz, batch, precision, direction, torch.cuda.current_device())
@@ -251,5 +367,5 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-__all__ = ["Plan", "PlanMany", "get_plan", "quantize", "dequantize", "scaled16_bytes", "fftn", "ifftn", "Fft3dError", "FFT3D_FORWARD",
+__all__ = ["Plan", "PlanMany", "RealPlan", "rfftn", "irfftn", "get_plan", "quantize", "dequantize", "scaled16_bytes", "fftn", "ifftn", "Fft3dError", "FFT3D_FORWARD",
            "FFT3D_INVERSE", "FFT3D_FP32", "FFT3D_FP16_SCALED", "FFT3D_BF16_SCALED"]

@@ -243,6 +243,89 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
     return p;
 }
 
+fft3d_plan_t fft3d_plan_real(int nx, int ny, int nz, int batch, int direction)
+{
+    clear_error();
+    if (nx < 1 || ny < 1 || nz < 1 || batch < 1) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
+    if (direction != FFT3D_FORWARD && direction != FFT3D_INVERSE) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
+    if (!size_supported(nx) || !size_supported(ny) || !size_supported(nz)) {
+        set_error(FFT3D_E_UNSUPPORTED_SIZE);
+        return nullptr;
+    }
+    if (nx != ny || nx % 2 || !real_plane_fn(nx, direction < 0)) { set_error(FFT3D_E_UNSUPPORTED); return nullptr; }
+    const long vol = (long)nx * ny * nz;
+    if ((long)batch * vol > (1L << 36)) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
+    int ndev = 0, dev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1 || hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(FFT3D_E_NO_DEVICE);
+        return nullptr;
+    }
+    fft3d_plan_s* p = new (std::nothrow) fft3d_plan_s{};
+    if (!p) { set_error(FFT3D_E_ALLOC); return nullptr; }
+    p->nx = nx; p->ny = ny; p->nz = nz; p->batch = batch;
+    p->precision = FFT3D_FP32; p->direction = direction; p->device = dev; p->vol = vol;
+    p->real = true;
+    p->scheme = kPlaneZ;
+    const int M = nx / 2, H = M + 1;
+    std::vector<float2> tab;
+    auto append = [&](const std::vector<float2>& t) {
+        const long off = (long)tab.size();
+        tab.insert(tab.end(), t.begin(), t.end());
+        if (tab.size() % 2) tab.push_back(make_float2(0.f, 0.f));
+        return off;
+    };
+    p->tw_x = append(twiddles(M, direction));
+    p->tw_y = append(twiddles(ny, direction));
+    p->tw_z = append(twiddles(nz, direction));
+    // split/merge roots exp(direction * 2 pi i k / nx), k = 0 .. M/2
+    std::vector<float2> rt(M / 2 + 1);
+    for (int k = 0; k <= M / 2; ++k) {
+        const double a = 2.0 * M_PI * (double)k / (double)nx;
+        rt[k] = make_float2((float)std::cos(a), (float)(direction * std::sin(a)));
+    }
+    p->tw_rt = append(rt);
+    const size_t bytes = tab.size() * sizeof(float2);
+    if (test_fail_alloc() || hipMalloc((void**)&p->d_tw, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        set_error(FFT3D_E_ALLOC);
+        return nullptr;
+    }
+    if (hipMemcpy(p->d_tw, tab.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(p->d_tw);
+        delete p;
+        set_error(FFT3D_E_LAUNCH);
+        return nullptr;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+        (void)hipGetLastError();
+        cus = 1;
+    }
+    const long planes = (long)batch * nz;
+    const long resident = (long)real_blocks_per_cu(nx, direction < 0) * cus;
+    const Pass plane{Pass::kRealK, nx, planes, {}, 0, (int)(planes < resident ? planes : resident)};
+    // z pass over the half layout [batch][z][y][H]
+    const AxisMap zmap{(long)batch * ny * H, H, ny, (long)nz * ny * H, (long)H, (long)ny * H};
+    const Pass zpass{Pass::kStrK, nz, 0, zmap, p->tw_z, 0};
+    if (direction == FFT3D_FORWARD) {
+        p->passes.push_back(plane);
+        if (nz > 1) p->passes.push_back(zpass);
+    } else {
+        if (nz > 1) p->passes.push_back(zpass);
+        p->passes.push_back(plane);
+    }
+    return p;
+}
+
+size_t fft3d_real_bytes(fft3d_plan_t p)
+{
+    if (!p || !p->real) return 0;
+    return (size_t)p->batch * (size_t)p->vol * sizeof(float);
+}
+
 int fft3d_destroy(fft3d_plan_t p)
 {
     if (!p) return FFT3D_OK;
@@ -253,6 +336,7 @@ int fft3d_destroy(fft3d_plan_t p)
     if (p->mp.d_items) (void)hipFree(p->mp.d_items);
     if (p->mp.d_twoff) (void)hipFree(p->mp.d_twoff);
     if (p->d_zlist) (void)hipFree(p->d_zlist);
+    if (p->d_rows) (void)hipFree(p->d_rows);
     delete p;
     return FFT3D_OK;
 }
@@ -266,6 +350,8 @@ size_t fft3d_buffer_bytes(fft3d_plan_t p)
             b += (size_t)p->mp.batch[g] * p->mp.n[g] * p->mp.n[g] * p->mp.n[g] * sizeof(float2);
         return b;
     }
+    if (p->real)   // the complex half-spectrum side
+        return (size_t)p->batch * p->nz * p->ny * (p->nx / 2 + 1) * sizeof(float2);
     if (p->precision != FFT3D_FP32)   // payload (4 B per point) + one exponent byte per x-row
         return (size_t)p->batch * (size_t)p->vol * 4 + (size_t)p->batch * p->nz * p->ny;
     return (size_t)p->batch * (size_t)p->vol * sizeof(float2);
@@ -284,8 +370,12 @@ static hipError_t run_pass(const fft3d_plan_s* p, const Pass& ps, const float2* 
     case Pass::kRowK: return axis_row_fn(ps.n, S)(src, dst, tw, ps.count, st);
     case Pass::kStrK: return axis_str_fn(ps.n, S)(src, dst, tw, ps.map, 0, nullptr, nullptr, 0, st);
     case Pass::kPlanePrunedK:
-        return plane_pruned_fn(ps.n, S)(src, dst, tw, ps.count, ps.grid, p->d_zlist, p->n_zlist, p->nz, p->cut_r2, st);
-    case Pass::kStrPrunedK: return axis_str_pruned_fn(ps.n, S)(src, dst, tw, ps.map, p->cut_r2, st);
+        return plane_pruned_fn(ps.n, S)(src, dst, tw, ps.count, ps.grid, p->d_zlist, p->n_zlist, p->nz, p->cut_r2,
+                                        nullptr, 0, st);
+    case Pass::kStrPrunedK: return axis_str_pruned_fn(ps.n, S)(src, dst, tw, ps.map, p->cut_r2, nullptr, 0, st);
+    case Pass::kRealK:
+        return real_plane_fn(ps.n, S < 0)(src, dst, p->d_tw + p->tw_x, p->d_tw + p->tw_y, p->d_tw + p->tw_rt,
+                                          ps.count, ps.grid, st);
     case Pass::kQ16PlaneK:
     case Pass::kQ16SlabK: {
         const size_t pay = (size_t)p->batch * p->vol * 4;
@@ -322,6 +412,21 @@ int fft3d_exec(fft3d_plan_t p, const void* in, void* out, fft3d_stream_t stream)
     const float2* src = static_cast<const float2*>(in);
     float2* dst = static_cast<float2*>(out);
     hipError_t e = hipSuccess;
+    if (p->real) {
+        // r2c: plane pass in -> out, z pass in place on out.  c2r: z pass in
+        // place on the input (which it overwrites), plane pass in -> out.
+        if (in == out) return FFT3D_E_INVALID_ARG;
+        float2* work = p->direction == FFT3D_INVERSE ? const_cast<float2*>(src) : dst;
+        for (size_t i = 0; i < p->passes.size() && e == hipSuccess; ++i) {
+            const Pass& ps = p->passes[i];
+            e = ps.kind == Pass::kRealK ? run_pass(p, ps, src, dst, st) : run_pass(p, ps, work, work, st);
+        }
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return FFT3D_E_LAUNCH;
+        }
+        return FFT3D_OK;
+    }
     for (size_t i = 0; i < p->passes.size() && e == hipSuccess; ++i)
         e = run_pass(p, p->passes[i], i == 0 ? src : dst, dst, st);
     if (e == hipSuccess && p->passes.empty() && src != dst)
@@ -345,8 +450,18 @@ int fft3d_exec_pass(fft3d_plan_t p, int pass, const void* in, void* out, fft3d_s
     const int rc = check_ptrs(p, in, out);
     if (rc != FFT3D_OK) return rc;
     if (p->many || pass < 0 || pass >= (int)p->passes.size()) return FFT3D_E_INVALID_ARG;
-    const hipError_t e = run_pass(p, p->passes[pass], static_cast<const float2*>(in), static_cast<float2*>(out),
-                                  reinterpret_cast<hipStream_t>(stream));
+    const Pass& ps = p->passes[pass];
+    const float2* src = static_cast<const float2*>(in);
+    float2* dst = static_cast<float2*>(out);
+    if (p->real && ps.kind != Pass::kRealK) {
+        // the z pass of a real plan works in place on the complex (half
+        // spectrum) side: `out` of an r2c, `in` of a c2r; the other pointer
+        // may be the smaller real buffer and is never touched by it
+        float2* work = p->direction == FFT3D_INVERSE ? const_cast<float2*>(src) : dst;
+        src = work;
+        dst = work;
+    }
+    const hipError_t e = run_pass(p, ps, src, dst, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return FFT3D_E_LAUNCH;
@@ -376,7 +491,8 @@ static int energy_args(fft3d_plan_t p, const void* a, const void* b, const void*
     if (!p || !a || !b || !V || !d) return FFT3D_E_INVALID_ARG;
     if (((uintptr_t)a % 16) || ((uintptr_t)b % 16) || ((uintptr_t)V % 16) || ((uintptr_t)d % 8))
         return FFT3D_E_ALIGNMENT;
-    if (p->many || p->precision != FFT3D_FP32 || p->nx != p->ny || !p->partials) return FFT3D_E_UNSUPPORTED;
+    if (p->many || p->real || p->precision != FFT3D_FP32 || p->nx != p->ny || !p->partials)
+        return FFT3D_E_UNSUPPORTED;
     return FFT3D_OK;
 }
 
@@ -477,7 +593,7 @@ int fft3d_plan_set_cutoff(fft3d_plan_t p, double r2)
 {
     if (!p) return FFT3D_E_INVALID_ARG;
     if (!(r2 == r2)) return FFT3D_E_INVALID_ARG;   // NaN
-    if (p->many || p->precision != FFT3D_FP32 || p->nx != p->ny) return FFT3D_E_UNSUPPORTED;
+    if (p->many || p->real || p->precision != FFT3D_FP32 || p->nx != p->ny) return FFT3D_E_UNSUPPORTED;
     const int nx = p->nx, nz = p->nz;
     if (!plane_pruned_fn(nx, p->direction) || !axis_str_pruned_fn(nz, p->direction)) return FFT3D_E_UNSUPPORTED;
     if (p->dense_passes.empty()) p->dense_passes = p->passes;
@@ -485,8 +601,10 @@ int fft3d_plan_set_cutoff(fft3d_plan_t p, double r2)
         p->passes = p->dense_passes;
         p->cut_r2 = 0;
         p->n_zlist = 0;
+        p->sphere_pts = 0;
         return FFT3D_OK;
     }
+    const int ny = p->ny;
     // planes kz whose signed frequency satisfies Gz^2 < r2, in ascending kz;
     // the z pass applies the same test element by element
     std::vector<int> zl;
@@ -494,19 +612,45 @@ int fft3d_plan_set_cutoff(fft3d_plan_t p, double r2)
         const int g = signed_freq(k, nz);
         if ((double)(g * g) < r2) zl.push_back(k);
     }
+    // packed-sphere rows: the points of row (kz, ky) inside the sphere are
+    // kx = 0 .. npos-1 and the last cnt - npos ones, by the same test
+    std::vector<SphereRow> rows((size_t)nz * ny);
+    long pts = 0;
+    for (int kz = 0; kz < nz; ++kz)
+        for (int ky = 0; ky < ny; ++ky) {
+            const int gz = signed_freq(kz, nz), gy = signed_freq(ky, ny);
+            SphereRow r{(int)pts, 0, 0, 0};
+            for (int kx = 0; kx < nx; ++kx) {
+                const int gx = signed_freq(kx, nx);
+                if ((double)(gx * gx + gy * gy + gz * gz) < r2) {
+                    ++r.cnt;
+                    if (gx >= 0) ++r.npos;
+                }
+            }
+            rows[(size_t)kz * ny + ky] = r;
+            pts += r.cnt;
+        }
     int* d = nullptr;
-    if (test_fail_alloc() || hipMalloc((void**)&d, sizeof(int) * zl.size()) != hipSuccess) {
+    SphereRow* dr = nullptr;
+    if (test_fail_alloc() || hipMalloc((void**)&d, sizeof(int) * zl.size()) != hipSuccess ||
+        hipMalloc((void**)&dr, sizeof(SphereRow) * rows.size()) != hipSuccess) {
         (void)hipGetLastError();
+        if (d) (void)hipFree(d);
         return FFT3D_E_ALLOC;
     }
-    if (hipMemcpy(d, zl.data(), sizeof(int) * zl.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(d, zl.data(), sizeof(int) * zl.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dr, rows.data(), sizeof(SphereRow) * rows.size(), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(d);
+        (void)hipFree(dr);
         return FFT3D_E_LAUNCH;
     }
     if (p->d_zlist) (void)hipFree(p->d_zlist);
+    if (p->d_rows) (void)hipFree(p->d_rows);
     p->d_zlist = d;
+    p->d_rows = dr;
     p->n_zlist = (int)zl.size();
+    p->sphere_pts = pts;
     p->cut_r2 = r2;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1) {
@@ -525,10 +669,97 @@ int fft3d_plan_set_cutoff(fft3d_plan_t p, double r2)
     return FFT3D_OK;
 }
 
+long long fft3d_plan_sphere_points(fft3d_plan_t p)
+{
+    if (!p) return FFT3D_E_INVALID_ARG;
+    if (p->cut_r2 <= 0) return FFT3D_E_UNSUPPORTED;
+    return p->sphere_pts;
+}
+
+static int sphere_copy(fft3d_plan_t p, bool pack, const void* src, void* dst, fft3d_stream_t stream)
+{
+    const int rc = check_ptrs(p, src, dst);
+    if (rc != FFT3D_OK) return rc;
+    if (p->cut_r2 <= 0 || p->many) return FFT3D_E_UNSUPPORTED;
+    if (src == dst) return FFT3D_E_INVALID_ARG;
+    const long total = (long)p->batch * p->vol;
+    const hipError_t e = launch_sphere_copy(pack, static_cast<const float2*>(src), static_cast<float2*>(dst), p->d_rows,
+                                            p->sphere_pts, p->nx, (long)p->nz * p->ny, total,
+                                            reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
+int fft3d_sphere_pack(fft3d_plan_t p, const void* dense, void* packed, fft3d_stream_t stream)
+{
+    return sphere_copy(p, true, dense, packed, stream);
+}
+
+int fft3d_sphere_unpack(fft3d_plan_t p, const void* packed, void* dense, fft3d_stream_t stream)
+{
+    return sphere_copy(p, false, packed, dense, stream);
+}
+
+int fft3d_exec_packed(fft3d_plan_t p, void* dense, void* packed, fft3d_stream_t stream)
+{
+    const int rc = check_ptrs(p, dense, packed);
+    if (rc != FFT3D_OK) return rc;
+    if (p->cut_r2 <= 0 || p->many) return FFT3D_E_UNSUPPORTED;
+    if (dense == packed) return FFT3D_E_INVALID_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    float2* d = static_cast<float2*>(dense);
+    float2* pk = static_cast<float2*>(packed);
+    const int S = p->direction;
+    hipError_t e = hipSuccess;
+    // the pass list of the cutoff schedule: [plane, z] (z only when nz > 1)
+    const Pass& plane = p->passes[0];
+    const float2* twp = p->d_tw + plane.tw;
+    if (S == FFT3D_INVERSE) {
+        e = plane_pruned_fn(plane.n, S)(pk, d, twp, plane.count, plane.grid, p->d_zlist, p->n_zlist, p->nz, p->cut_r2,
+                                        p->d_rows, p->sphere_pts, st);
+        if (e == hipSuccess && p->passes.size() > 1)
+            e = run_pass(p, p->passes[1], d, d, st);
+    } else {
+        e = run_pass(p, plane, d, d, st);
+        if (e == hipSuccess) {
+            if (p->passes.size() > 1) {
+                const Pass& z = p->passes[1];
+                e = axis_str_pruned_fn(z.n, S)(d, pk, p->d_tw + z.tw, z.map, p->cut_r2, p->d_rows, p->sphere_pts, st);
+            } else {
+                e = launch_sphere_copy(true, d, pk, p->d_rows, p->sphere_pts, p->nx, (long)p->nz * p->ny,
+                                       (long)p->batch * p->vol, st);
+            }
+        }
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
 int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
 {
     if (!p) return FFT3D_E_INVALID_ARG;
     if (p->many) return many_describe(p, buf, len);
+    if (p->real) {
+        const KernelInfo a = real_info(p->nx), b = axis_str_info(p->nz);
+        char t[256];
+        snprintf(t, sizeof t, "real %s n=%d half=%d threads=%d lds=%d planes=%ld; z n=%d threads=%d lds=%d kernels=%s",
+                 p->direction < 0 ? "r2c" : "c2r", p->nx, p->nx / 2 + 1, a.threads, a.lds_bytes,
+                 (long)p->batch * p->nz, p->nz, b.threads, b.lds_bytes,
+                 p->nz == 1 ? (p->direction < 0 ? "k_plane_r2c" : "k_plane_c2r")
+                            : (p->direction < 0 ? "k_plane_r2c,k_axis_str" : "k_axis_str,k_plane_c2r"));
+        const std::string d = t;
+        if (buf && len) {
+            std::strncpy(buf, d.c_str(), len - 1);
+            buf[len - 1] = 0;
+        }
+        return (int)d.size();
+    }
     auto radices = [](int n) {
         const Sched sc = make_sched(n);
         std::string s;
@@ -572,7 +803,8 @@ int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len)
     }
     d += p->direction < 0 ? " forward" : " inverse";
     if (p->cut_r2 > 0) {
-        snprintf(tmp, sizeof tmp, " cutoff_r2=%.17g zplanes=%d", p->cut_r2, p->n_zlist);
+        snprintf(tmp, sizeof tmp, " cutoff_r2=%.17g zplanes=%d sphere_points=%ld", p->cut_r2, p->n_zlist,
+                 p->sphere_pts);
         d += tmp;
     }
     d += " kernels=";

@@ -44,12 +44,23 @@ static hipError_t launch_axis_str(const float2* in, float2* out, const float2* t
 
 template <int N, int S>
 static hipError_t launch_axis_str_pruned(const float2* in, float2* out, const float2* tw, const AxisMap& m, double R2,
-                                         hipStream_t st)
+                                         const SphereRow* rows, long npts, hipStream_t st)
 {
     const long blocks = axis_str_blocks(m.lines);
-    // inverse plans prune the loads (sphere-limited input), forward plans lines and stores
+    // inverse plans prune the loads (sphere-limited input), forward plans
+    // lines and stores (optionally scattering into a packed sphere)
+    if constexpr (S < 0) {
+        if (rows) {
+            hipLaunchKernelGGL((k_axis_str<N, S, kAxisLines, false, 3>), dim3((unsigned)blocks),
+                               dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, out, tw, m, nullptr, nullptr, 0L, R2, rows,
+                               npts);
+            return hipGetLastError();
+        }
+    } else {
+        if (rows) return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL((k_axis_str<N, S, kAxisLines, false, (S > 0 ? 1 : 2)>), dim3((unsigned)blocks),
-                       dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, out, tw, m, nullptr, nullptr, 0L, R2);
+                       dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, out, tw, m, nullptr, nullptr, 0L, R2, nullptr, 0L);
     return hipGetLastError();
 }
 
@@ -63,6 +74,21 @@ AxisStrPrunedFn axis_str_pruned_fn(int n, int sign)
         FFT3D_FOR_EACH_SIZE(FFT3D_STR_PRUNED_CASE)
     default: return nullptr;
     }
+}
+
+hipError_t launch_sphere_copy(bool pack, const float2* src, float2* dst, const SphereRow* rows, long npts, int nx,
+                              long nyz, long total, hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    long blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;   // grid-stride beyond 2M points
+    if (pack)
+        hipLaunchKernelGGL((k_sphere_copy<true>), dim3((unsigned)blocks), dim3(256), 0, st, src, dst, rows, npts, nx,
+                           nyz, total);
+    else
+        hipLaunchKernelGGL((k_sphere_copy<false>), dim3((unsigned)blocks), dim3(256), 0, st, src, dst, rows, npts, nx,
+                           nyz, total);
+    return hipGetLastError();
 }
 
 template <int N, int S>

@@ -61,11 +61,22 @@ int plane_pf_blocks_per_cu(int n)
 
 template <int N, int S>
 static hipError_t launch_plane_pruned(const float2* in, float2* out, const float2* tw, long planes, int grid,
-                                      const int* zlist, int nzp, int nz, double R2, hipStream_t st)
+                                      const int* zlist, int nzp, int nz, double R2, const SphereRow* rows, long npts,
+                                      hipStream_t st)
 {
-    // inverse plans prune planes and row loads, forward plans the stores
-    hipLaunchKernelGGL((k_plane_pruned<N, S, (S < 0)>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out, tw, planes,
-                       zlist, nzp, nz, R2);
+    // inverse plans prune planes and row loads (optionally gathering from a
+    // packed sphere), forward plans the stores
+    if constexpr (S > 0) {
+        if (rows) {
+            hipLaunchKernelGGL((k_plane_pruned<N, S, false, true>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st,
+                               in, out, tw, planes, zlist, nzp, nz, R2, rows, npts);
+            return hipGetLastError();
+        }
+    } else {
+        if (rows) return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((k_plane_pruned<N, S, (S < 0)>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out,
+                       tw, planes, zlist, nzp, nz, R2, nullptr, 0L);
     return hipGetLastError();
 }
 

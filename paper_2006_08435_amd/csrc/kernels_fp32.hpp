@@ -381,6 +381,57 @@ k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long pl
 // Signed frequency of index k on a length-n axis (k for k < n/2, k - n above).
 __host__ __device__ __forceinline__ int signed_freq(int k, int n) { return 2 * k < n ? k : k - n; }
 
+// Packed sphere: the points of a grid inside the sphere, in the grid's own
+// order ([kz][ky][kx] ascending), grid after grid.  Row (kz, ky) of a grid
+// holds cnt of them at packed offset off: kx = 0 .. npos-1, then
+// kx = n - (cnt - npos) .. n - 1 (the non-negative, then the negative
+// frequencies).  The table has one entry per (kz, ky).
+struct SphereRow {
+    int off, cnt, npos, pad;
+};
+
+__host__ __device__ __forceinline__ bool sphere_has(const SphereRow& r, int x, int n)
+{
+    return x < r.npos || x >= n - (r.cnt - r.npos);
+}
+
+// Packed index (within the grid) of point kx = x of row r; x must be inside.
+__host__ __device__ __forceinline__ int sphere_rank(const SphereRow& r, int x, int n)
+{
+    return r.off + (x < r.npos ? x : x - (n - r.cnt));
+}
+
+// One N x N plane gathered from a packed sphere into registers (zeros at the
+// points outside it), in the element order of a plane tile.
+template <int N, int T>
+struct PackedRegs {
+    static constexpr int E = N * N;
+    static constexpr int IT = (E + T - 1) / T;
+    float2 r[IT];
+
+    __device__ __forceinline__ void load(const float2* packed, const SphereRow* rows, int tid)
+    {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (E % T == 0 || i < E) {
+                const int y = i / N, x = i % N;
+                const SphereRow rw = rows[y];
+                r[k] = sphere_has(rw, x, N) ? packed[sphere_rank(rw, x, N)] : make_float2(0.f, 0.f);
+            }
+        }
+    }
+    template <int RS>
+    __device__ __forceinline__ void store_lds(float2* lds, int tid) const
+    {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (E % T == 0 || i < E) lds[(i / N) * RS + (i % N)] = r[k];
+        }
+    }
+};
+
 // Plane output that stores only the points with Gx^2 + Gy^2 < R2.
 template <int N>
 struct PlaneColOutDisk {
@@ -405,22 +456,28 @@ struct PlaneColOutDisk {
 //     (`planes` = batch * nz, zlist unused) is read whole and transformed;
 //     only the points with Gx^2 + Gy^2 < R2, the z-lines the sphere meets,
 //     are written.
-template <int N, int S, bool OUT>
+//   PACKED (with OUT = false): `in` is a packed sphere of `npts` points per
+//     grid with row table `rows` ([kz][ky]); the rows are gathered from it.
+template <int N, int S, bool OUT, bool PACKED = false>
 __global__ void __launch_bounds__(PlaneGeom<N>::T)
 k_plane_pruned(const float2* in, float2* out, const float2* __restrict__ tw, long planes, const int* __restrict__ zlist,
-               int nzp, int nz, double R2)
+               int nzp, int nz, double R2, const SphereRow* __restrict__ rows = nullptr, long npts = 0)
 {
+    static_assert(!(OUT && PACKED), "the packed form of the plane pass is the inverse's");
     constexpr int T = PlaneGeom<N>::T, RS = PlaneGeom<N>::RS;
     __shared__ float2 lds[PlaneGeom<N>::WORDS];
     const int tid = threadIdx.x;
-    TileRegs<N, N, T> regs;
+    typename std::conditional<PACKED, PackedRegs<N, T>, TileRegs<N, N, T>>::type regs;
     auto plane_base = [&](long i) {
         if constexpr (OUT) return i * N * N;
         const long b = i / nzp;
         return (b * nz + zlist[i % nzp]) * (long)N * N;
     };
     auto load = [&](long i) {
-        if constexpr (OUT) {
+        if constexpr (PACKED) {
+            const long g = i / nzp;
+            regs.load(in + g * npts, rows + (long)zlist[i % nzp] * N, tid);
+        } else if constexpr (OUT) {
             regs.load(in + plane_base(i), tid);
         } else {
             const int gz = signed_freq(zlist[i % nzp], nz), gz2 = gz * gz;
@@ -447,6 +504,30 @@ k_plane_pruned(const float2* in, float2* out, const float2* __restrict__ tw, lon
             run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
         }
         __syncthreads();
+    }
+}
+
+// Dense grids [batch][nz][ny][nx] <-> packed spheres [batch][npts]
+// (PACK: gather the points inside the sphere; otherwise scatter them and
+// write zeros everywhere else).  nyz = nz * ny rows per grid.
+template <bool PACK>
+__global__ void __launch_bounds__(256)
+k_sphere_copy(const float2* __restrict__ src, float2* __restrict__ dst, const SphereRow* __restrict__ rows, long npts,
+              int nx, long nyz, long total)
+{
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const long row = i / nx;
+        const int x = (int)(i - row * nx);
+        const long b = row / nyz;
+        const SphereRow r = rows[row - b * nyz];
+        const bool in = sphere_has(r, x, nx);
+        const long p = b * npts + (in ? sphere_rank(r, x, nx) : 0);
+        if constexpr (PACK) {
+            if (in) dst[p] = src[i];
+        } else {
+            dst[i] = in ? src[p] : make_float2(0.f, 0.f);
+        }
     }
 }
 
@@ -773,15 +854,40 @@ struct GlobStridedPruned {
     }
 };
 
+// Z-line (x, y) of grid b in the last pass of the pruned forward with a
+// packed output: loads as GlobStridedPruned<2>; element z is stored to the
+// packed sphere when row (z, y) holds point x.
+struct GlobZPacked {
+    const float2* src;
+    float2* packed;                 // this grid's packed sphere
+    const SphereRow* rows;          // [kz][ky] table
+    long es;
+    int x, y, ny, nx;
+    bool line_in;                   // Gx^2 + Gy^2 < R2
+    __device__ __forceinline__ float2 load(int, int e) const
+    {
+        return line_in ? src[(long)e * es] : make_float2(0.f, 0.f);
+    }
+    __device__ __forceinline__ void store(int, int e, float2 v) const
+    {
+        if (!line_in) return;
+        const SphereRow r = rows[(long)e * ny + y];
+        if (sphere_has(r, x, nx)) packed[sphere_rank(r, x, nx)] = v;
+    }
+};
+
 // ENERGY: the pass is the last one of an inverse transform psi = IFFT(c);
 // while storing psi it accumulates sum V |psi|^2 and writes one FP64 partial
 // per workgroup to partials[blockIdx.x] (V indexed by position in the grid).
 // PRUNE: 0 dense; 1 z pass of the pruned inverse, 2 z pass of the pruned
-// forward (GlobStridedPruned; both require the z-pass AxisMap).
+// forward (GlobStridedPruned), 3 z pass of the pruned forward into a packed
+// sphere (GlobZPacked: `out` is the packed buffer, npts points per grid).
+// 1 to 3 require the z-pass AxisMap.
 template <int N, int S, int L, bool ENERGY = false, int PRUNE = 0>
 __global__ void __launch_bounds__((AxisGeom<N, L>::T))
 k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap m, const float* __restrict__ V,
-           double* __restrict__ partials, long vol, double R2 = 0.0)
+           double* __restrict__ partials, long vol, double R2 = 0.0, const SphereRow* __restrict__ rows = nullptr,
+           long npts = 0)
 {
     using G = AxisGeom<N, L>;
     using P = Plan1D<N>;
@@ -813,6 +919,21 @@ k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap
         }
         const double t = block_sum<T>(eg.acc, red, tid);
         if (tid == 0) partials[blockIdx.x] = t;
+    } else if constexpr (PRUNE == 3) {
+        const long o = li / m.nx;
+        const int x = (int)(li - o * m.nx), y = (int)(o % m.odiv);
+        const long b = o / m.odiv;
+        const int gx = signed_freq(x, (int)m.nx), gy = signed_freq(y, (int)m.odiv);
+        const GlobZPacked gp{in + gbase, out + b * npts, rows, m.es, x, y, (int)m.odiv, (int)m.nx,
+                             (double)(gx * gx + gy * gy) < R2 && li < m.lines};
+        if constexpr (P::stages == 1) {
+            fft_stage<N, 0, S, L, T, true, false>(gp, gp, tw, tid, valid);
+        } else {
+            const LdsAcc<1, G::LP> a{lds};
+            fft_stage<N, 0, S, L, T, true, false>(gp, a, tw, tid, valid);
+            __syncthreads();
+            run_tail<N, S, L, T, 1, false>(a, gp, tw, tid, valid);
+        }
     } else if constexpr (PRUNE != 0) {
         int gxy2 = 0;
         if constexpr (PRUNE == 2) {   // z pass: line li = (b * ny + y) * nx + x with odiv = ny

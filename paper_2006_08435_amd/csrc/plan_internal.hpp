@@ -23,7 +23,7 @@ std::vector<float2> twiddles(int n, int sign, int kind = 0);
 // One kernel launch of an exec.  The first pass reads the caller's input,
 // every later pass works in place on the output buffer.
 struct Pass {
-    enum Kind { kCubeK, kPlaneK, kPlanePfK, kRowK, kStrK, kFusedK, kQ16PlaneK, kQ16SlabK, kPlanePrunedK, kStrPrunedK } kind;
+    enum Kind { kCubeK, kPlaneK, kPlanePfK, kRowK, kStrK, kFusedK, kQ16PlaneK, kQ16SlabK, kPlanePrunedK, kStrPrunedK, kRealK } kind;
     int n;        // transform length of this pass
     long count;   // grids / planes / rows (cube, plane, row kinds)
     AxisMap map;  // strided kind
@@ -75,7 +75,11 @@ struct fft3d_plan_s {
     double cut_r2;             // > 0: sphere cutoff of the pruned inverse (fft3d_plan_set_cutoff)
     int* d_zlist;              // z-planes with Gz^2 < cut_r2 (device), n_zlist of them
     int n_zlist;
+    fft3d::SphereRow* d_rows;  // packed-sphere row table [nz][ny] (device)
+    long sphere_pts;           // points per grid inside the cutoff sphere
     std::vector<fft3d::Pass> dense_passes;   // schedule without the cutoff
+    bool real;                 // plan from fft3d_plan_real (r2c forward / c2r inverse)
+    long tw_rt;                // real plans: offset of the split/merge roots W_N^{direction*k}, k <= N/4
     bool many;                 // plan from fft3d_plan_many
     fft3d::ManyPlan mp;
 };

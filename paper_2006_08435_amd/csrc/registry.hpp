@@ -9,6 +9,7 @@ namespace fft3d {
 struct AxisMap;
 struct FusedCtl;
 struct ManyArgs;
+struct SphereRow;
 
 using CubeFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long grids, hipStream_t st);
 using PlaneFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, hipStream_t st);
@@ -41,10 +42,17 @@ PlanePfFn plane_pf_fn(int n, int sign);
 // Forward (sign -1, output wanted inside the sphere only): plane pass over
 // every plane storing only the z-lines the sphere meets, then the z pass
 // over those lines storing only the sphere.
+// rows != nullptr selects the packed-sphere forms: the inverse plane pass
+// gathers its input from a packed sphere of npts points per grid, the
+// forward z pass scatters its output into one.
 using PlanePrunedFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, int grid,
-                                     const int* zlist, int nzp, int nz, double R2, hipStream_t st);
+                                     const int* zlist, int nzp, int nz, double R2, const SphereRow* rows, long npts,
+                                     hipStream_t st);
 using AxisStrPrunedFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, const AxisMap& m, double R2,
-                                       hipStream_t st);
+                                       const SphereRow* rows, long npts, hipStream_t st);
+// Dense [batch][nz][ny][nx] <-> packed [batch][npts] (pack: gather, else scatter with zeros).
+hipError_t launch_sphere_copy(bool pack, const float2* src, float2* dst, const SphereRow* rows, long npts, int nx,
+                              long nyz, long total, hipStream_t st);
 PlanePrunedFn plane_pruned_fn(int n, int sign);
 AxisStrPrunedFn axis_str_pruned_fn(int n, int sign);
 int plane_pf_blocks_per_cu(int n);
@@ -88,5 +96,14 @@ KernelInfo axis_str_info(int n);
 KernelInfo axis_row_info(int n);
 KernelInfo fused_info(int n);
 KernelInfo q16_info(int n);
+
+// Real-grid plane passes (Nx = Ny = n even): r2c (forward) real planes ->
+// half-spectrum planes [n][n/2+1], c2r (inverse) the reverse.  tw_x is the
+// length-n/2 table, tw_y the length-n table, rt the split/merge roots.
+using RealPlaneFn = hipError_t (*)(const void* in, void* out, const float2* tw_x, const float2* tw_y,
+                                   const float2* rt, long planes, int grid, hipStream_t st);
+RealPlaneFn real_plane_fn(int n, bool forward);
+int real_blocks_per_cu(int n, bool forward);
+KernelInfo real_info(int n);
 
 }  // namespace fft3d

@@ -70,6 +70,11 @@ def test_null_handles():
     assert lib.fft3d_exec(None, None, None, None) == -1
     assert lib.fft3d_plan_describe(None, None, 0) == -1
     assert lib.fft3d_plan_set_cutoff(None, 10.0) == -1
+    assert lib.fft3d_plan_sphere_points(None) == -1
+    assert lib.fft3d_sphere_pack(None, None, None, None) == -1
+    assert lib.fft3d_sphere_unpack(None, None, None, None) == -1
+    assert lib.fft3d_exec_packed(None, None, None, None) == -1
+    assert lib.fft3d_real_bytes(None) == 0
 
 
 def test_strerror_covers_codes():
