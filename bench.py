@@ -57,7 +57,10 @@ def measured_traffic(workload: str, kernel: str):
         d = json.load(f)
     if d.get("source_hash") != source_hash():
         return None
-    k = d.get("kernels", {}).get(kernel)
+    ks = d.get("kernels", {})
+    k = ks.get(kernel)
+    if k is None:   # a prefix of the profiler's kernel name, e.g. "k_plane_pf<128, 1"
+        k = next((v for name, v in sorted(ks.items()) if name.startswith(kernel)), None)
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
@@ -183,7 +186,8 @@ def main(argv=None):
     achieved = bytes_per_transform / (dom["ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.workload, dom_name),
+                "traffic": measured_traffic(args.workload, "%s<%d, %s" % (
+                    dom_name, n, "-1" if dom["transform"] == "forward" else "1")),
                 "kernel": "%s<%d,%s>" % (dom_name, n, "-1" if dom["transform"] == "forward" else "1"),
                 "ms_per_launch": round(dom["ms"], 5)}
 
@@ -485,8 +489,9 @@ def bench_pruned(args):
     pk = [k for k in pass_bytes]
     dom = max(pk, key=lambda k: times[k])
     achieved = pass_bytes[dom] / (times[dom] * 1e-3) / 1e9
-    kern = {"inverse_pass0": "k_plane_pruned<128,1,false>", "inverse_pass1": "k_axis_str<128,1,64,false,1>",
-            "forward_pass0": "k_plane_pruned<128,-1,true>", "forward_pass1": "k_axis_str<128,-1,64,false,2>"}
+    kern = {"inverse_pass0": "k_plane_pruned<128, 1, false, false>", "inverse_pass1": "k_axis_str<128, 1, 64, false, 1>",
+            "forward_pass0": "k_plane_pruned<128, -1, true, false>",
+            "forward_pass1": "k_axis_str<128, -1, 64, false, 2>"}
     rec.update({
         "times_ms": dict({"pruned_step": round(pruned_ms, 4), "dense_step": round(dense_ms, 4),
                           "speedup": round(dense_ms / pruned_ms, 3),
@@ -571,8 +576,8 @@ def bench_real(args):
                        {"n": n, "batch": B, "precision": "fp32", "input": "uniform real grids"})
     dom = max(pass_bytes, key=lambda k: times[k])
     achieved = pass_bytes[dom] / (times[dom] * 1e-3) / 1e9
-    kern = {"r2c_pass0": "k_plane_r2c<128,-1>", "r2c_pass1": "k_axis_str<128,-1,64> (half layout)",
-            "c2r_pass0": "k_axis_str<128,1,64> (half layout)", "c2r_pass1": "k_plane_c2r<128,1>"}
+    kern = {"r2c_pass0": "k_plane_r2c<128, -1>", "r2c_pass1": "k_axis_str<128, -1, 64, false, 0>",
+            "c2r_pass0": "k_axis_str<128, 1, 64, false, 0>", "c2r_pass1": "k_plane_c2r<128, 1>"}
     rec.update({
         "times_ms": {k: round(v, 4) for k, v in times.items()},
         "algorithmic_bytes": dict({"step": total}, **pass_bytes),
