@@ -32,6 +32,8 @@ WORKLOADS = {
     "single128": (128, 1, 2128, "c2c 3D FFT, one 128^3 grid, inverse then forward, complex64"),
     "single64": (64, 1, 2064, "c2c 3D FFT, one 64^3 grid, inverse then forward, complex64"),
     "batch64": (64, 256, 4000, "c2c 3D FFT, 256 grids of 64^3, inverse then forward, complex64"),
+    "big256": (256, 4, 6000, "c2c 3D FFT, 4 grids of 256^3 (three-pass form), inverse then forward, complex64"),
+    "big512": (512, 1, 6100, "c2c 3D FFT, one 512^3 grid (three-pass form), inverse then forward, complex64"),
 }
 EXTRA_WORKLOADS = ("mixed", "energy96", "fp16_128", "bf16_128", "pruned128", "real128")
 

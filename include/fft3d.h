@@ -73,7 +73,7 @@ enum fft3d_direction {
 enum fft3d_status {
     FFT3D_OK = 0,
     FFT3D_E_INVALID_ARG = -1,      /* NULL plan/pointer, bad enum, batch < 1, size < 1 */
-    FFT3D_E_UNSUPPORTED_SIZE = -2, /* a dimension > 128 or not of the form 2^a 3^b 5^c */
+    FFT3D_E_UNSUPPORTED_SIZE = -2, /* a dimension > 512 or not of the form 2^a 3^b 5^c */
     FFT3D_E_NO_DEVICE = -3,        /* no usable HIP device */
     FFT3D_E_ALLOC = -4,            /* device allocation failed at plan time */
     FFT3D_E_LAUNCH = -5,           /* a kernel launch or HIP call failed */
@@ -84,10 +84,15 @@ enum fft3d_status {
 
 /*
  * Create a plan for `batch` grids of nx * ny * nz points (Section II, Eq. (1)).
- * 1 <= nx, ny, nz <= 128, each 2^a 3^b 5^c; batch >= 1; precision one of
+ * 1 <= nx, ny, nz <= 512, each 2^a 3^b 5^c; batch >= 1; precision one of
  * fft3d_precision; direction FFT3D_FORWARD or FFT3D_INVERSE.  Builds the
  * radix schedule, generates the twiddle factors in double precision (rounded
  * once to the working precision) and uploads them to the current device.
+ * Grids with a dimension above 128 (the larger sizes the paper names as
+ * future work, Section III) use the three-pass form: one 1D pass per axis
+ * (x rows, then strided y and z lines), FP32 only (FFT3D_E_UNSUPPORTED for
+ * the scaled 16-bit precisions); every other entry point that takes a plan
+ * (energy, cutoff, real grids, heterogeneous batches) is limited to 128.
  * Returns NULL on error (see fft3d_last_error).
  */
 fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int direction);
@@ -96,8 +101,8 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
  * Real grids.  Densities and potentials, the other grids a plane-wave code
  * transforms (Section I), are real; their transform under Eq. (1) is
  * Hermitian, F(-k) = conj F(k), so half of it is kept: kx = 0 .. nx/2.
- * Plan `batch` real transforms with nx == ny, nx even (each dimension as in
- * fft3d_plan), FP32.
+ * Plan `batch` real transforms with nx == ny, nx even, each dimension
+ * 2^a 3^b 5^c in 1..128, FP32.
  *   FORWARD (r2c): in = real float32 [batch][nz][ny][nx], out = complex64
  *     [batch][nz][ny][nx/2 + 1], the kx <= nx/2 half of Eq. (1).
  *   INVERSE (c2r): in = complex64 [batch][nz][ny][nx/2 + 1], out = real

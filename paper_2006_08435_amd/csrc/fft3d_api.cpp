@@ -81,7 +81,7 @@ const char* fft3d_strerror(int code)
     switch (code) {
     case FFT3D_OK: return "success";
     case FFT3D_E_INVALID_ARG: return "invalid argument";
-    case FFT3D_E_UNSUPPORTED_SIZE: return "unsupported size (each dimension must be 2^a 3^b 5^c, 1..128)";
+    case FFT3D_E_UNSUPPORTED_SIZE: return "unsupported size (each dimension must be 2^a 3^b 5^c, 1..512)";
     case FFT3D_E_NO_DEVICE: return "no usable HIP device";
     case FFT3D_E_ALLOC: return "device allocation failed";
     case FFT3D_E_LAUNCH: return "kernel launch or HIP call failed";
@@ -103,10 +103,14 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
         return nullptr;
     }
     if (direction != FFT3D_FORWARD && direction != FFT3D_INVERSE) { set_error(FFT3D_E_INVALID_ARG); return nullptr; }
-    if (!size_supported(nx) || !size_supported(ny) || !size_supported(nz)) {
+    auto size_ok = [](int n) { return size_supported(n) || size_supported_large(n); };
+    if (!size_ok(nx) || !size_ok(ny) || !size_ok(nz)) {
         set_error(FFT3D_E_UNSUPPORTED_SIZE);
         return nullptr;
     }
+    // lengths above 128: FP32, three-pass form only
+    const bool large = nx > 128 || ny > 128 || nz > 128;
+    if (large && precision != FFT3D_FP32) { set_error(FFT3D_E_UNSUPPORTED); return nullptr; }
     const long vol = (long)nx * ny * nz;
     // 2^36 points (512 GiB of complex64) bounds every grid dimension of every
     // launch below 2^31 workgroups.
@@ -131,6 +135,7 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
         p->scheme = kQ16;
         p->q16_valu = env_flag("FFT3D_Q16_VALU");
     }
+    else if (large) p->scheme = kAxes;
     else if (nx == ny && ny == nz && nx <= kCubeMaxN) p->scheme = kCube;
     else if (nx == ny && ny == nz && fused_fn(nx, direction) && fused_mode() > 0) p->scheme = kFused;
     else if (nx == ny) p->scheme = kPlaneZ;
@@ -169,7 +174,7 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
         set_error(FFT3D_E_LAUNCH);
         return nullptr;
     }
-    if (nx == ny && !q16) {
+    if (nx == ny && !q16 && !large) {
         // energy path: persistent plane pass + strided z pass with fused epilogue
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;

@@ -116,6 +116,7 @@ static hipError_t launch_axis_row(const float2* in, float2* out, const float2* t
 
 AxisStrFn axis_str_fn(int n, int sign)
 {
+    if (n > 128) return axis_str_large_fn(n, sign);
     switch (n) {
         FFT3D_FOR_EACH_SIZE(FFT3D_STR_CASE)
     default: return nullptr;
@@ -124,6 +125,7 @@ AxisStrFn axis_str_fn(int n, int sign)
 
 AxisRowFn axis_row_fn(int n, int sign)
 {
+    if (n > 128) return axis_row_large_fn(n, sign);
     switch (n) {
         FFT3D_FOR_EACH_SIZE(FFT3D_ROW_CASE)
     default: return nullptr;
@@ -132,6 +134,7 @@ AxisRowFn axis_row_fn(int n, int sign)
 
 KernelInfo axis_str_info(int n)
 {
+    if (n > 128) return axis_str_large_info(n);
     switch (n) {
         FFT3D_FOR_EACH_SIZE(FFT3D_STR_INFO)
     default: return {0, 0};
@@ -140,6 +143,7 @@ KernelInfo axis_str_info(int n)
 
 KernelInfo axis_row_info(int n)
 {
+    if (n > 128) return axis_row_large_info(n);
     switch (n) {
         FFT3D_FOR_EACH_SIZE(FFT3D_ROW_INFO)
     default: return {0, 0};

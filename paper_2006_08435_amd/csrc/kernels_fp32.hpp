@@ -984,10 +984,10 @@ k_axis_row(const float2* in, float2* out, const float2* __restrict__ tw, long ro
     const long r0 = (long)blockIdx.x * L;
     const int valid = (int)((rows - r0) < L ? (rows - r0) : L);
     const long base = r0 * N;
-    for (int i = tid; i < valid * N; i += T) lds[(i / N) * G::RS + (i % N)] = in[base + i];
+    tile_to_lds<L, N, G::RS, T>(in + base, lds, tid, valid);
     __syncthreads();
     fft_lds_all<N, S, L, T, G::RS, 1>(lds, tw, tid, valid);
-    for (int i = tid; i < valid * N; i += T) out[base + i] = lds[(i / N) * G::RS + (i % N)];
+    lds_to_tile<L, N, G::RS, T>(lds, out + base, tid, valid);
 }
 
 }  // namespace fft3d

@@ -96,6 +96,12 @@ KernelInfo axis_str_info(int n);
 KernelInfo axis_row_info(int n);
 KernelInfo fused_info(int n);
 KernelInfo q16_info(int n);
+// Lengths above 128 (three-pass form only); axis_str_fn / axis_row_fn and
+// their _info functions forward to these for n > 128.
+AxisStrFn axis_str_large_fn(int n, int sign);
+AxisRowFn axis_row_large_fn(int n, int sign);
+KernelInfo axis_str_large_info(int n);
+KernelInfo axis_row_large_info(int n);
 
 // Real-grid plane passes (Nx = Ny = n even): r2c (forward) real planes ->
 // half-spectrum planes [n][n/2+1], c2r (inverse) the reverse.  tw_x is the

@@ -1,7 +1,7 @@
 // Radix schedules and twiddle-table geometry shared by the host planner and
 // the device kernels of the FP32 path.
 //
-// A 1D transform of length N (2*3*5-smooth, 1 <= N <= 128) is computed as a
+// A 1D transform of length N (2*3*5-smooth, 1 <= N <= 512) is computed as a
 // sequence of self-sorting (Stockham) radix-R stages.  Stage s has radix r[s]
 // and "span" NS(s) = r[0] * ... * r[s-1]; its butterfly j reads elements
 // j + q*N/R (q < R), multiplies element q by W_{NS*R}^{(j mod NS) q}, applies
@@ -37,7 +37,9 @@ __host__ __device__ constexpr Sched make_sched(int n)
     case 4: s.r[s.count++] = 16; break;
     case 5: s.r[s.count++] = 8; s.r[s.count++] = 4; break;
     case 6: s.r[s.count++] = 8; s.r[s.count++] = 8; break;
-    default: s.r[s.count++] = 8; s.r[s.count++] = 16; break;   // 128
+    case 7: s.r[s.count++] = 8; s.r[s.count++] = 16; break;
+    case 8: s.r[s.count++] = 16; s.r[s.count++] = 16; break;
+    default: s.r[s.count++] = 8; s.r[s.count++] = 8; s.r[s.count++] = 8; break;   // 512
     }
     while (m % 3 == 0) { s.r[s.count++] = 3; m /= 3; }
     while (m % 5 == 0) { s.r[s.count++] = 5; m /= 5; }
@@ -96,15 +98,21 @@ __host__ __device__ constexpr int sched_min_radix(const Sched& s)
     return m;
 }
 
-// Supported lengths: 2*3*5-smooth, 1..128.
-__host__ __device__ constexpr bool size_supported(int n)
+__host__ __device__ constexpr bool smooth235(int n)
 {
-    if (n < 1 || n > 128) return false;
+    if (n < 1) return false;
     while (n % 2 == 0) n /= 2;
     while (n % 3 == 0) n /= 3;
     while (n % 5 == 0) n /= 5;
     return n == 1;
 }
+
+// Lengths of every form: 2*3*5-smooth, 1..128.
+__host__ __device__ constexpr bool size_supported(int n) { return n <= 128 && smooth235(n); }
+
+// Lengths of the three-pass form only (one line of up to 512 points per
+// transform, lines of 16..32 per workgroup): 2*3*5-smooth, 129..512.
+__host__ __device__ constexpr bool size_supported_large(int n) { return n > 128 && n <= 512 && smooth235(n); }
 
 }  // namespace fft3d
 
@@ -121,3 +129,9 @@ __host__ __device__ constexpr bool size_supported(int n)
     X(20) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(45) X(48) X(50) X(54)    \
     X(60) X(64) X(72) X(75) X(80) X(81) X(90) X(96) X(100) X(108) X(120)       \
     X(125) X(128)
+
+// X-macro over the lengths of the three-pass form above 128.
+#define FFT3D_FOR_EACH_LARGE_SIZE(X)                                           \
+    X(135) X(144) X(150) X(160) X(162) X(180) X(192) X(200) X(216) X(225)      \
+    X(240) X(243) X(250) X(256) X(270) X(288) X(300) X(320) X(324) X(360)      \
+    X(375) X(384) X(400) X(405) X(432) X(450) X(480) X(486) X(500) X(512)

@@ -54,7 +54,8 @@ def test_no_undeclared_c_exports():
     ((16, 16, 16, -3, 0, -1), -1), ((16, 16, 16, 1, 3, -1), -1), ((16, 16, 16, 1, -1, -1), -1),
     ((16, 16, 16, 1, 0, 0), -1), ((16, 16, 16, 1, 0, 2), -1),
     ((7, 16, 16, 1, 0, -1), -2), ((16, 11, 16, 1, 0, -1), -2), ((16, 16, 129, 1, 0, -1), -2),
-    ((256, 16, 16, 1, 0, -1), -2), ((14, 16, 16, 1, 0, -1), -2),
+    ((1024, 16, 16, 1, 0, -1), -2), ((14, 16, 16, 1, 0, -1), -2), ((16, 16, 514, 1, 0, -1), -2),
+    ((16, 16, 1000, 1, 0, -1), -2), ((256, 256, 256, 1, 1, -1), -7), ((16, 512, 16, 1, 2, 1), -7),
 ])
 def test_plan_rejects_bad_arguments(args, code):
     L = _lib()
