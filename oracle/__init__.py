@@ -81,6 +81,7 @@ def _bind(lib):
     lib.oracle_q16_encode.argtypes = [ci, ctypes.c_long, ci, fp, u16, i8]
     lib.oracle_q16_decode.argtypes = [ci, ctypes.c_long, ci, u16, i8, dp]
     lib.oracle_energy.argtypes = [ci, ci, ci, ci, dp, dp, dp, dp, dp]
+    lib.oracle_apply_potential.argtypes = [ci, ci, ci, ci, dp, dp, dp]
     lib.oracle_r2c3d.argtypes = [ci, ci, ci, ci, dp, dp]
     lib.oracle_c2r3d.argtypes = [ci, ci, ci, ci, dp, dp]
     return lib
@@ -174,6 +175,20 @@ def fft3d(a, sign: int = -1, order=(0, 1, 2)) -> np.ndarray:
     o = (ctypes.c_int * 3)(*[int(v) for v in order])
     _check(lib.oracle_fft3d_order(nx, ny, nz, b, int(sign),
                                   _ptr(x, ctypes.c_double), _ptr(out, ctypes.c_double), o))
+    return out[0] if squeeze else out
+
+
+def apply_potential(c, V) -> np.ndarray:
+    """forward(V * inverse(c)) per grid (unnormalised both ways)."""
+    lib = _load()
+    x, squeeze = _shape3(c)
+    b, nz, ny, nx = x.shape
+    v = np.ascontiguousarray(V, dtype=np.float64)
+    if v.shape != (nz, ny, nx):
+        raise ValueError("V must be [z, y, x] of the grid shape")
+    out = np.empty_like(x)
+    _check(lib.oracle_apply_potential(nx, ny, nz, b, _ptr(x, ctypes.c_double), _ptr(v, ctypes.c_double),
+                                      _ptr(out, ctypes.c_double)))
     return out[0] if squeeze else out
 
 

@@ -490,6 +490,32 @@ int oracle_q16_decode(int fmt, long rows, int row_len, const uint16_t *payload,
  * inverse is the unnormalised forward transform.
  * psi and grad may be NULL.
  */
+/*
+ * The local-potential operator of a plane-wave code applied to coefficient
+ * grids c_n: out_n = forward transform (sign -1) of V * inverse transform
+ * (sign +1) of c_n, both unnormalised (so a constant V = v gives
+ * out = v * Nx*Ny*Nz * c).  This is half the gradient of the energy below.
+ */
+int oracle_apply_potential(int nx, int ny, int nz, int batch, const double *c,
+                           const double *V, double *out)
+{
+    const long vol = (long)nx * ny * nz;
+    const int inverse = +1, forward = -1;
+    double *p = malloc(sizeof(double) * 2 * vol * batch);
+    if (!p) return -4;
+    int err = oracle_fft3d(nx, ny, nz, batch, inverse, c, p);
+    if (!err) {
+        for (int b = 0; b < batch; ++b)
+            for (long i = 0; i < vol; ++i) {
+                p[2 * (b * vol + i)] *= V[i];
+                p[2 * (b * vol + i) + 1] *= V[i];
+            }
+        err = oracle_fft3d(nx, ny, nz, batch, forward, p, out);
+    }
+    free(p);
+    return err;
+}
+
 int oracle_energy(int nx, int ny, int nz, int batch, const double *c,
                   const double *V, double *E, double *psi, double *grad)
 {

@@ -307,6 +307,27 @@ def pin_real():
     assert np.max(np.abs(H - want)) < 1e-10
 
 
+def pin_apply_potential():
+    """forward(V inverse(c)): numpy witness, constant potential, self-adjointness
+    (<a, H b> = <H a, b> for real V), and half the energy gradient."""
+    nx, ny, nz, b = 6, 4, 5, 2
+    c = rand_grid((b, nz, ny, nx), 500)
+    V = np.random.default_rng(501).uniform(-1, 2, (nz, ny, nx))
+    vol = nx * ny * nz
+    H = oracle.apply_potential(c, V)
+    want = np.fft.fftn(V * np.fft.ifftn(c, axes=(-3, -2, -1)) * vol, axes=(-3, -2, -1))
+    assert rel(H, want) < 1e-13
+    const = oracle.apply_potential(c, np.full((nz, ny, nx), 0.75))
+    assert rel(const, 0.75 * vol * c) < 1e-13
+    a = rand_grid((nz, ny, nx), 502)
+    d = rand_grid((nz, ny, nx), 503)
+    lhs = np.vdot(a, oracle.apply_potential(d, V))
+    rhs = np.vdot(oracle.apply_potential(a, V), d)
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+    _, _, grad = oracle.energy(c, V, want_grad=True)
+    assert rel(H, grad / 2) < 1e-13
+
+
 ALL_PINS = [pin_golden, pin_closed_forms, pin_naive_vs_numpy, pin_fft_vs_naive,
             pin_fft_vs_numpy, pin_invariants, pin_fp16_rounding, pin_bf16_rounding,
-            pin_q16_rule, pin_energy, pin_real]
+            pin_q16_rule, pin_energy, pin_real, pin_apply_potential]

@@ -63,3 +63,7 @@ def test_rejects_bad_arguments():
 
 def test_real_transforms():
     P.pin_real()
+
+
+def test_apply_potential():
+    P.pin_apply_potential()

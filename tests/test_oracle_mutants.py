@@ -35,6 +35,10 @@ MUTANTS = {
     "c2r Nyquist sign": ("((x & 1) ? -H[2 * (nx / 2)] : H[2 * (nx / 2)])", "H[2 * (nx / 2)]"),
     "c2r sin sign": ("- H[2 * k + 1] * w[2 * e + 1]", "+ H[2 * k + 1] * w[2 * e + 1]"),
     "c2r skips z": ("if (!err) err = axis_pass(h, ny, nz, batch, +1, 2, t);", "(void)0;"),
+    "apply uses forward first": ("oracle_fft3d(nx, ny, nz, batch, inverse, c, p);",
+                                 "oracle_fft3d(nx, ny, nz, batch, forward, c, p);"),
+    "apply skips V imag": ("                p[2 * (b * vol + i) + 1] *= V[i];\n            }\n        err = oracle_fft3d(nx, ny, nz, batch, forward, p, out);",
+                           "            }\n        err = oracle_fft3d(nx, ny, nz, batch, forward, p, out);"),
     "r2c wrong half": ("out[2 * (r * h + k)] = full[2 * (r * nx + k)];",
                        "out[2 * (r * h + k)] = full[2 * (r * nx + (nx - k) % nx)];"),
 }
