@@ -300,8 +300,9 @@ int fft3d_plan_tune(fft3d_plan_t plan);
  *     2 * gE_dev[0] * V * psi_n -- the gradient of gE * E in the convention
  *     dE/dRe(c) + i dE/dIm(c) (the adjoint of the unnormalised inverse is the
  *     unnormalised forward transform).  If have_psi != 0, c_or_psi holds psi
- *     (e.g. from fft3d_energy_fwd); otherwise it holds c and psi is
- *     recomputed into grad_c first.  grad_c may equal c_or_psi.
+ *     (e.g. from fft3d_energy_fwd); otherwise it holds c and the gradient
+ *     is computed by the fused operator below (psi is not stored).  grad_c
+ *     may equal c_or_psi.
  *
  * Both enqueue on `stream` without host synchronisation.  Returns FFT3D_OK,
  * FFT3D_E_INVALID_ARG (NULL pointer), FFT3D_E_ALIGNMENT (data not 16-byte,
@@ -310,6 +311,26 @@ int fft3d_plan_tune(fft3d_plan_t plan);
  */
 int fft3d_energy_fwd(fft3d_plan_t plan, const void *c, const float *V, void *psi, double *E_dev,
                      fft3d_stream_t stream);
+
+/*
+ * The local-potential operator itself, out_n = s * forward(V * inverse(c_n))
+ * (both unnormalised; s = scale_dev[0] if scale_dev is not NULL, else 1):
+ * the product of Section I's operator evaluation, and half the energy
+ * gradient.  Three passes instead of four: inverse xy planes, then one
+ * fused z kernel (inverse z transform, the energy sum and the product with
+ * V, forward z transform, with psi held on chip and never written to HBM),
+ * then forward xy planes.  If E_dev is not NULL it receives
+ * E = sum_n sum_r V(r) |psi_n(r)|^2 as in fft3d_energy_fwd.  With a cutoff
+ * set on the plan (fft3d_plan_set_cutoff) the pruned passes are used: c must
+ * vanish outside the sphere, and only the points of `out` inside the sphere
+ * are written (the rest are unspecified).  c == out is allowed.  The
+ * forward transform runs z before xy, so results agree with fft3d_exec's
+ * forward to FP32 rounding.  Plans as for the energy entry points; returns
+ * the same codes.  fft3d_energy_bwd with have_psi == 0 uses this path (with
+ * s = 2 gE, dense).
+ */
+int fft3d_apply_potential(fft3d_plan_t plan, const void *c, const float *V, void *out, double *E_dev,
+                          const double *scale_dev, fft3d_stream_t stream);
 int fft3d_energy_bwd(fft3d_plan_t plan, const void *c_or_psi, int have_psi, const float *V, const double *gE_dev,
                      void *grad_c, fft3d_stream_t stream);
 

@@ -113,6 +113,20 @@ class Plan:
                                                 _stream_handle(stream)), "fft3d_exec_packed")
         return dense if self.direction == FFT3D_INVERSE else packed
 
+    def apply_potential(self, c, V, out=None, E=None, scale=None, stream=None):
+        """out = scale * forward(V * inverse(c)) (``fft3d_apply_potential``);
+        E (a 0-d float64 device tensor) receives sum V |inverse(c)|^2."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(c)
+        for t in (c, out, V):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("tensors must be contiguous device tensors")
+        ptr = lambda t: 0 if t is None else t.data_ptr()
+        _lib.check(_lib.lib().fft3d_apply_potential(self._h, c.data_ptr(), V.data_ptr(), out.data_ptr(), ptr(E),
+                                                    ptr(scale), _stream_handle(stream)), "fft3d_apply_potential")
+        return out
+
     def exec_ptr(self, in_ptr: int, out_ptr: int, stream_handle: int) -> None:
         _lib.check(_lib.lib().fft3d_exec(self._h, in_ptr, out_ptr, stream_handle), "fft3d_exec")
 

@@ -516,6 +516,64 @@ int fft3d_energy_fwd(fft3d_plan_t p, const void* c, const float* V, void* psi, d
     return FFT3D_OK;
 }
 
+// out = mult * s * forward(V * inverse(c)), s = scale ? scale[0] : 1, in three
+// passes: inverse xy planes (c -> out), the fused z kernel (inverse z, V,
+// forward z; psi stays on chip), forward xy planes (out -> out).  With
+// `cut` and a cutoff on the plan, the passes are the pruned ones (input
+// zero outside the sphere, output defined inside it).  E (optional): sum
+// V |inverse(c)|^2.
+static hipError_t hloc_run(const fft3d_plan_s* p, const float2* c, float2* out, const float* V, double* E,
+                           const double* scale, float mult, bool cut, hipStream_t st)
+{
+    const int n = p->nx, nz = p->nz;
+    const bool inv_plan = p->direction == FFT3D_INVERSE;
+    const float2* twx_inv = p->d_tw + (inv_plan ? p->tw_x : p->tw_rx);
+    const float2* twx_fwd = p->d_tw + (inv_plan ? p->tw_rx : p->tw_x);
+    const float2* twz_inv = p->d_tw + (inv_plan ? p->tw_z : p->tw_rz);
+    const float2* twz_fwd = p->d_tw + (inv_plan ? p->tw_rz : p->tw_z);
+    const AxisMap zmap{(long)p->batch * p->ny * n, n, p->ny, p->vol, (long)n, (long)n * p->ny};
+    double* partials = E ? p->partials : nullptr;
+    hipError_t e;
+    if (cut) {
+        const long planes = (long)p->batch * p->n_zlist;
+        const int grid = (int)(planes < p->pf_grid ? planes : p->pf_grid);
+        e = plane_pruned_fn(n, FFT3D_INVERSE)(c, out, twx_inv, planes, grid, p->d_zlist, p->n_zlist, nz, p->cut_r2,
+                                              nullptr, 0, st);
+        if (e == hipSuccess)
+            e = axis_hloc_fn(nz)(out, twz_inv, twz_fwd, zmap, V, scale, mult, partials, p->vol, p->cut_r2, 1, st);
+        if (e == hipSuccess)
+            e = plane_ball_fwd_fn(n)(out, out, twx_fwd, planes, grid, p->d_zlist, p->n_zlist, nz, p->cut_r2, nullptr,
+                                     0, st);
+    } else {
+        const long planes = (long)p->batch * nz;
+        e = plane_pf_fn(n, FFT3D_INVERSE)(c, out, twx_inv, planes, p->pf_grid, 0, nullptr, nullptr, nz, st);
+        if (e == hipSuccess)
+            e = axis_hloc_fn(nz)(out, twz_inv, twz_fwd, zmap, V, scale, mult, partials, p->vol, 0.0, 0, st);
+        if (e == hipSuccess)
+            e = plane_pf_fn(n, FFT3D_FORWARD)(out, out, twx_fwd, planes, p->pf_grid, 0, nullptr, nullptr, nz, st);
+    }
+    if (e == hipSuccess && E) e = launch_sum_partials(p->partials, p->n_partials, E, st);
+    return e;
+}
+
+int fft3d_apply_potential(fft3d_plan_t p, const void* c, const float* V, void* out, double* E_dev,
+                          const double* scale_dev, fft3d_stream_t stream)
+{
+    if (!p || !c || !V || !out) return FFT3D_E_INVALID_ARG;
+    if (((uintptr_t)c % 16) || ((uintptr_t)out % 16) || ((uintptr_t)V % 16) || ((uintptr_t)E_dev % 8) ||
+        ((uintptr_t)scale_dev % 8))
+        return FFT3D_E_ALIGNMENT;
+    if (p->many || p->real || p->precision != FFT3D_FP32 || p->nx != p->ny || !p->partials)
+        return FFT3D_E_UNSUPPORTED;
+    const hipError_t e = hloc_run(p, static_cast<const float2*>(c), static_cast<float2*>(out), V, E_dev, scale_dev,
+                                  1.0f, p->cut_r2 > 0, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
 int fft3d_energy_bwd(fft3d_plan_t p, const void* c_or_psi, int have_psi, const float* V, const double* gE_dev,
                      void* grad_c, fft3d_stream_t stream)
 {
@@ -525,11 +583,10 @@ int fft3d_energy_bwd(fft3d_plan_t p, const void* c_or_psi, int have_psi, const f
     const float2* src = static_cast<const float2*>(c_or_psi);
     float2* g = static_cast<float2*>(grad_c);
     hipError_t e = hipSuccess;
-    if (!have_psi) {   // recompute psi = IFFT(c) into the gradient buffer
-        e = energy_transform(p, FFT3D_INVERSE, src, g, nullptr, nullptr, false, st);
-        src = g;
-    }
-    if (e == hipSuccess) e = energy_transform(p, FFT3D_FORWARD, src, g, V, gE_dev, false, st);
+    if (!have_psi)   // from c: the fused operator, 2 gE forward(V inverse(c)), psi never stored
+        e = hloc_run(p, src, g, V, nullptr, gE_dev, 2.0f, false, st);
+    else
+        e = energy_transform(p, FFT3D_FORWARD, src, g, V, gE_dev, false, st);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return FFT3D_E_LAUNCH;

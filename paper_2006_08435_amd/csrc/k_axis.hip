@@ -76,6 +76,33 @@ AxisStrPrunedFn axis_str_pruned_fn(int n, int sign)
     }
 }
 
+template <int N>
+static hipError_t launch_hloc(float2* buf, const float2* tw_inv, const float2* tw_fwd, const AxisMap& m,
+                              const float* V, const double* scale, float mult, double* partials, long vol, double R2,
+                              int mode, hipStream_t st)
+{
+    const long blocks = axis_str_blocks(m.lines);
+    if (mode)
+        hipLaunchKernelGGL((k_axis_hloc<N, kAxisLines, 1>), dim3((unsigned)blocks), dim3(AxisGeom<N, kAxisLines>::T),
+                           0, st, buf, tw_inv, tw_fwd, m, V, scale, mult, partials, vol, R2);
+    else
+        hipLaunchKernelGGL((k_axis_hloc<N, kAxisLines, 0>), dim3((unsigned)blocks), dim3(AxisGeom<N, kAxisLines>::T),
+                           0, st, buf, tw_inv, tw_fwd, m, V, scale, mult, partials, vol, R2);
+    return hipGetLastError();
+}
+
+#define FFT3D_HLOC_CASE(n)                                                     \
+    case n:                                                                    \
+        return &launch_hloc<n>;
+
+HlocFn axis_hloc_fn(int n)
+{
+    switch (n) {
+        FFT3D_FOR_EACH_SIZE(FFT3D_HLOC_CASE)
+    default: return nullptr;
+    }
+}
+
 hipError_t launch_sphere_copy(bool pack, const float2* src, float2* dst, const SphereRow* rows, long npts, int nx,
                               long nyz, long total, hipStream_t st)
 {

@@ -68,16 +68,40 @@ static hipError_t launch_plane_pruned(const float2* in, float2* out, const float
     // packed sphere), forward plans the stores
     if constexpr (S > 0) {
         if (rows) {
-            hipLaunchKernelGGL((k_plane_pruned<N, S, false, true>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st,
+            hipLaunchKernelGGL((k_plane_pruned<N, S, 0, true>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st,
                                in, out, tw, planes, zlist, nzp, nz, R2, rows, npts);
             return hipGetLastError();
         }
     } else {
         if (rows) return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL((k_plane_pruned<N, S, (S < 0)>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out,
-                       tw, planes, zlist, nzp, nz, R2, nullptr, 0L);
+    hipLaunchKernelGGL((k_plane_pruned<N, S, (S < 0 ? 1 : 0)>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st,
+                       in, out, tw, planes, zlist, nzp, nz, R2, nullptr, 0L);
     return hipGetLastError();
+}
+
+// Forward plane pass over the planes of zlist, storing only the sphere
+// (the last pass of the local-potential operator with a cutoff).
+template <int N>
+static hipError_t launch_plane_ball(const float2* in, float2* out, const float2* tw, long planes, int grid,
+                                    const int* zlist, int nzp, int nz, double R2, const SphereRow*, long,
+                                    hipStream_t st)
+{
+    hipLaunchKernelGGL((k_plane_pruned<N, -1, 2>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out, tw,
+                       planes, zlist, nzp, nz, R2, nullptr, 0L);
+    return hipGetLastError();
+}
+
+#define FFT3D_PLANE_BALL_CASE(n)                                               \
+    case n:                                                                    \
+        return &launch_plane_ball<n>;
+
+PlanePrunedFn plane_ball_fwd_fn(int n)
+{
+    switch (n) {
+        FFT3D_FOR_EACH_SIZE(FFT3D_PLANE_BALL_CASE)
+    default: return nullptr;
+    }
 }
 
 #define FFT3D_PLANE_PRUNED_CASE(n)                                             \

@@ -445,6 +445,21 @@ struct PlaneColOutDisk {
     }
 };
 
+// Plane output of plane kz (gz2 = Gz^2) storing only the points inside the
+// sphere Gx^2 + Gy^2 + gz2 < R2.
+template <int N>
+struct PlaneColOutBall {
+    float2* p;
+    int gz2;
+    double R2;
+    __device__ __forceinline__ float2 load(int, int) const { return float2{}; }
+    __device__ __forceinline__ void store(int x, int y, float2 v) const
+    {
+        const int gx = signed_freq(x, N), gy = signed_freq(y, N);
+        if ((double)(gx * gx + gy * gy + gz2) < R2) p[y * N + x] = v;
+    }
+};
+
 // The xy-plane pass of a pruned transform with the sphere |G|^2 < R2
 // (G = signed frequencies) on grids [batch][nz][N][N].
 //   OUT = false (inverse, input vanishing outside the sphere): only the
@@ -452,18 +467,23 @@ struct PlaneColOutDisk {
 //     batch * nzp) are transformed, and in each only the rows with
 //     Gy^2 + Gz^2 < R2 are read, the other rows being zeros.  Whole planes
 //     are written; the other planes are neither read nor written.
-//   OUT = true (forward, output wanted inside the sphere only): every plane
+//   KIND 1 (forward, output wanted inside the sphere only): every plane
 //     (`planes` = batch * nz, zlist unused) is read whole and transformed;
 //     only the points with Gx^2 + Gy^2 < R2, the z-lines the sphere meets,
 //     are written.
-//   PACKED (with OUT = false): `in` is a packed sphere of `npts` points per
-//     grid with row table `rows` ([kz][ky]); the rows are gathered from it.
-template <int N, int S, bool OUT, bool PACKED = false>
+//   KIND 2 (last pass of a forward whose z pass came first, output wanted
+//     inside the sphere only): only the planes of zlist are read (whole) and
+//     transformed, and only their points inside the sphere are written.
+//   KIND 0 is the inverse (first form above).
+//   PACKED (with KIND 0): `in` is a packed sphere of `npts` points per grid
+//     with row table `rows` ([kz][ky]); the rows are gathered from it.
+template <int N, int S, int KIND, bool PACKED = false>
 __global__ void __launch_bounds__(PlaneGeom<N>::T)
 k_plane_pruned(const float2* in, float2* out, const float2* __restrict__ tw, long planes, const int* __restrict__ zlist,
                int nzp, int nz, double R2, const SphereRow* __restrict__ rows = nullptr, long npts = 0)
 {
-    static_assert(!(OUT && PACKED), "the packed form of the plane pass is the inverse's");
+    constexpr bool OUT = KIND == 1;
+    static_assert(KIND == 0 || !PACKED, "the packed form of the plane pass is the inverse's");
     constexpr int T = PlaneGeom<N>::T, RS = PlaneGeom<N>::RS;
     __shared__ float2 lds[PlaneGeom<N>::WORDS];
     const int tid = threadIdx.x;
@@ -477,7 +497,7 @@ k_plane_pruned(const float2* in, float2* out, const float2* __restrict__ tw, lon
         if constexpr (PACKED) {
             const long g = i / nzp;
             regs.load(in + g * npts, rows + (long)zlist[i % nzp] * N, tid);
-        } else if constexpr (OUT) {
+        } else if constexpr (KIND != 0) {
             regs.load(in + plane_base(i), tid);
         } else {
             const int gz = signed_freq(zlist[i % nzp], nz), gz2 = gz * gz;
@@ -496,8 +516,12 @@ k_plane_pruned(const float2* in, float2* out, const float2* __restrict__ tw, lon
         if (pn < planes) load(pn);
         fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
         const LdsAcc<1, RS> col{lds};
-        if constexpr (OUT) {
+        if constexpr (KIND == 1) {
             const PlaneColOutDisk<N> dst{out + plane_base(p), R2};
+            run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
+        } else if constexpr (KIND == 2) {
+            const int gz = signed_freq(zlist[p % nzp], nz);
+            const PlaneColOutBall<N> dst{out + plane_base(p), gz * gz, R2};
             run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
         } else {
             const PlaneColOut<N> dst{out + plane_base(p)};
@@ -965,6 +989,83 @@ k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap
 
 
 // --------------------------------------------------------------- x rows --
+
+// The z part of the local-potential operator of a plane-wave code,
+// out = forward(V * inverse(c)) with the transforms split as [inverse xy
+// planes] [this kernel] [forward xy planes]: each workgroup takes L adjacent
+// z-lines of the intermediate `buf`, runs the inverse z-transform into LDS
+// (psi of those lines, which never reaches HBM), accumulates sum V |psi|^2
+// (one FP64 partial per workgroup), multiplies psi by s V with
+// s = mult * (scale ? scale[0] : 1), runs the forward z-transform and stores
+// in place.  MODE 1 (sphere cutoff R2): only the elements with Gz^2 < R2 are
+// loaded (the others were never written by the pruned inverse plane pass)
+// and stored (the pruned forward plane pass reads only those planes).
+template <int N, int L, int MODE>
+__global__ void __launch_bounds__((AxisGeom<N, L>::T))
+k_axis_hloc(float2* buf, const float2* __restrict__ tw_inv, const float2* __restrict__ tw_fwd, AxisMap m,
+            const float* __restrict__ V, const double* __restrict__ scale, float mult, double* __restrict__ partials,
+            long vol, double R2)
+{
+    using G = AxisGeom<N, L>;
+    using P = Plan1D<N>;
+    constexpr int T = G::T;
+    static_assert(T % L == 0, "each thread keeps one line");
+    __shared__ float2 lds[G::WORDS];
+    __shared__ double red[T / 64];
+    const int tid = threadIdx.x;
+    const long l0 = (long)blockIdx.x * L;
+    const int myline = tid % L;
+    const long li = l0 + myline;
+    const int valid = (int)((m.lines - l0) < L ? (m.lines - l0) : L);
+    long gbase = 0;
+    if (li < m.lines) {
+        const long o = li / m.nx;
+        const long x = li - o * m.nx;
+        gbase = (o / m.odiv) * m.shi + (o % m.odiv) * m.slo + x;
+    }
+    using Acc = typename std::conditional<MODE == 1, GlobStridedPruned<1>, GlobStrided>::type;
+    using Out = typename std::conditional<MODE == 1, GlobStridedPruned<2>, GlobStrided>::type;
+    Acc src{};
+    Out dst{};
+    if constexpr (MODE == 1) {
+        src = Acc{buf + gbase, buf + gbase, m.es, N, 0, R2};
+        dst = Out{buf + gbase, buf + gbase, m.es, N, 0, R2};
+    } else {
+        src = Acc{buf + gbase, buf + gbase, m.es};
+        dst = Out{buf + gbase, buf + gbase, m.es};
+    }
+    const LdsAcc<1, G::LP> a{lds};
+    // inverse z-transform into LDS
+    fft_stage<N, 0, 1, L, T, true, false>(src, a, tw_inv, tid, valid);
+    __syncthreads();
+    if constexpr (P::stages > 1) {
+        run_tail<N, 1, L, T, 1, true>(a, a, tw_inv, tid, valid);
+        __syncthreads();
+    }
+    // psi -> energy partial, s V psi
+    const float s = mult * (scale ? (float)scale[0] : 1.f);
+    double acc = 0.0;
+    if (myline < valid) {
+        const float* v = V + (gbase % vol);
+        for (int e = tid / L; e < N; e += T / L) {
+            const float2 p = lds[e * G::LP + myline];
+            const float vv = v[(long)e * m.es];
+            acc += (double)(vv * fmaf(p.x, p.x, p.y * p.y));
+            const float f = s * vv;
+            lds[e * G::LP + myline] = make_float2(f * p.x, f * p.y);
+        }
+    }
+    const double t = block_sum<T>(acc, red, tid);   // contains the barrier before the forward stages
+    if (tid == 0 && partials) partials[blockIdx.x] = t;
+    // forward z-transform, stored in place
+    if constexpr (P::stages == 1) {
+        fft_stage<N, 0, -1, L, T, true, false>(a, dst, tw_fwd, tid, valid);
+    } else {
+        fft_stage<N, 0, -1, L, T, true, true>(a, a, tw_fwd, tid, valid);
+        __syncthreads();
+        run_tail<N, -1, L, T, 1, false>(a, dst, tw_fwd, tid, valid);
+    }
+}
 
 template <int N, int L>
 struct RowGeom {

@@ -54,6 +54,15 @@ using AxisStrPrunedFn = hipError_t (*)(const float2* in, float2* out, const floa
 hipError_t launch_sphere_copy(bool pack, const float2* src, float2* dst, const SphereRow* rows, long npts, int nx,
                               long nyz, long total, hipStream_t st);
 PlanePrunedFn plane_pruned_fn(int n, int sign);
+// Forward plane pass over the planes of zlist storing only the sphere.
+PlanePrunedFn plane_ball_fwd_fn(int n);
+// z part of the local-potential operator (see k_axis_hloc); mode 1 = cutoff
+// R2 (loads and stores limited to Gz^2 < R2).  partials: one FP64 per
+// workgroup (axis_str_blocks(m.lines) of them), may be null.
+using HlocFn = hipError_t (*)(float2* buf, const float2* tw_inv, const float2* tw_fwd, const AxisMap& m,
+                              const float* V, const double* scale, float mult, double* partials, long vol, double R2,
+                              int mode, hipStream_t st);
+HlocFn axis_hloc_fn(int n);
 AxisStrPrunedFn axis_str_pruned_fn(int n, int sign);
 int plane_pf_blocks_per_cu(int n);
 AxisStrFn axis_str_fn(int n, int sign);
