@@ -44,18 +44,40 @@ MUTANTS = {
 }
 
 
+# Each mutant runs in a child process: a planted indexing mistake (a wrong
+# stride, say) can write outside the oracle's buffers, and that must not
+# corrupt the test runner's own heap.  The child loads the mutant, runs the
+# pins until one fails, prints its name and leaves without running any
+# destructor.
+_CHILD = r"""
+import os, sys
+sys.path.insert(0, {tests!r})
+sys.path.insert(0, {root!r})
+import oracle
+import oracle_pins as P
+with oracle.variant({lib!r}):
+    for pin in P.ALL_PINS:
+        try:
+            pin()
+        except Exception as e:
+            print("CAUGHT", pin.__name__, type(e).__name__, flush=True)
+            os._exit(0)
+print("MISSED", flush=True)
+os._exit(0)
+"""
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_mutant(name, tmp_path):
+    import os
+    import subprocess
+    import sys
     old, new = MUTANTS[name]
     src = oracle.source_text()
     assert src.count(old) == 1, "mutation site not found: %s" % name
     lib = oracle.build_variant(src.replace(old, new), str(tmp_path / "libmutant.so"))
-    caught = []
-    with oracle.variant(lib):
-        for pin in P.ALL_PINS:
-            try:
-                pin()
-            except Exception as e:          # noqa: BLE001 -- any failure counts
-                caught.append((pin.__name__, type(e).__name__))
-                break
-    assert caught, "no pin caught mutant %r" % name
+    here = os.path.dirname(os.path.abspath(__file__))
+    code = _CHILD.format(tests=here, root=os.path.dirname(here), lib=lib)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert "CAUGHT" in r.stdout, "no pin caught mutant %r (exit %d): %s %s" % (name, r.returncode, r.stdout,
+                                                                            r.stderr[-500:])
