@@ -1,4 +1,5 @@
-// Register-resident R-point DFT butterflies (R = 1, 2, 3, 4, 5, 8, 16) on
+// Register-resident R-point DFT butterflies (R = 1, 2, 3, 4, 5, 6, 8, 9, 10,
+// 12, 15, 16) on
 // float2 complex values, for exponent sign S (-1 forward, +1 inverse):
 //   X[k] = sum_n x[n] exp(S * 2 pi i n k / R),  in place on v[0..R).
 // Constants are written to float precision from their closed forms.
@@ -137,6 +138,74 @@ template <int S> __device__ __forceinline__ void dft16(float2* v)
     t = v[11]; v[11] = v[14]; v[14] = t;
 }
 
+template <int R, int S> __device__ __forceinline__ void dft(float2* v);
+
+// Index k in [0, R1 R2) with k = k1 (mod R1) and k = k2 (mod R2) (Chinese
+// remainder map; R1, R2 coprime).
+template <int R1, int R2>
+__host__ __device__ constexpr int crt_index(int k1, int k2)
+{
+    for (int k = 0; k < R1 * R2; ++k)
+        if (k % R1 == k1 && k % R2 == k2) return k;
+    return 0;
+}
+
+// R1 R2 points with R1, R2 coprime by the prime-factor (Good-Thomas) mapping:
+// input n = (n1 R2 + n2 R1) mod R and output k = CRT(k1, k2) turn the DFT
+// into R2 DFTs of length R1 followed by R1 DFTs of length R2 with no
+// twiddle factors.  All indices are compile-time constants, so the
+// permutations are register renaming.
+template <int R1, int R2, int S> __device__ __forceinline__ void dft_pfa(float2* v)
+{
+    constexpr int R = R1 * R2;
+    float2 a[R2][R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2)
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) a[n2][n1] = v[(n1 * R2 + n2 * R1) % R];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) dft<R1, S>(a[n2]);
+    float2 b[R1][R2];
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1)
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) b[k1][n2] = a[n2][k1];
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) dft<R2, S>(b[k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) v[crt_index<R1, R2>(k1, k2)] = b[k1][k2];
+}
+
+// 9 points as 3 x 3: n = 3 n1 + n2, k = k1 + 3 k2, twiddles W9^(n2 k1).
+template <int S> __device__ __forceinline__ void dft9(float2* v)
+{
+    constexpr float C1 = 0.76604444311897804f, S1 = 0.64278760968653933f;    // 2 pi / 9
+    constexpr float C2 = 0.17364817766693035f, S2 = 0.98480775301220806f;    // 4 pi / 9
+    constexpr float C4 = -0.93969262078590838f, S4 = 0.34202014332566873f;   // 8 pi / 9
+    float2 a[3][3];   // a[n2][.]
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) {
+        a[n2][0] = v[n2];
+        a[n2][1] = v[3 + n2];
+        a[n2][2] = v[6 + n2];
+        dft3<S>(a[n2][0], a[n2][1], a[n2][2]);   // a[n2][k1]
+    }
+    a[1][1] = mul_cs<S>(a[1][1], C1, S1);
+    a[1][2] = mul_cs<S>(a[1][2], C2, S2);
+    a[2][1] = mul_cs<S>(a[2][1], C2, S2);
+    a[2][2] = mul_cs<S>(a[2][2], C4, S4);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+        float2 x0 = a[0][k1], x1 = a[1][k1], x2 = a[2][k1];
+        dft3<S>(x0, x1, x2);
+        v[k1] = x0;
+        v[k1 + 3] = x1;
+        v[k1 + 6] = x2;
+    }
+}
+
 template <int R, int S> __device__ __forceinline__ void dft(float2* v)
 {
     if constexpr (R == 1) {
@@ -148,8 +217,18 @@ template <int R, int S> __device__ __forceinline__ void dft(float2* v)
         dft4<S>(v[0], v[1], v[2], v[3]);
     } else if constexpr (R == 5) {
         dft5<S>(v[0], v[1], v[2], v[3], v[4]);
+    } else if constexpr (R == 6) {
+        dft_pfa<2, 3, S>(v);
     } else if constexpr (R == 8) {
         dft8<S>(v);
+    } else if constexpr (R == 9) {
+        dft9<S>(v);
+    } else if constexpr (R == 10) {
+        dft_pfa<2, 5, S>(v);
+    } else if constexpr (R == 12) {
+        dft_pfa<4, 3, S>(v);
+    } else if constexpr (R == 15) {
+        dft_pfa<3, 5, S>(v);
     } else if constexpr (R == 16) {
         dft16<S>(v);
     } else {

@@ -20,7 +20,80 @@ struct Sched {
     int r[8];
 };
 
+__host__ __device__ constexpr Sched make_sched_pow2(int n);
+
+// Radices with a register codelet.
+__host__ __device__ constexpr bool radix_ok(int r)
+{
+    return r == 2 || r == 3 || r == 4 || r == 5 || r == 6 || r == 8 || r == 9 || r == 10 || r == 12 || r == 15 ||
+           r == 16;
+}
+
+// Schedule of n: powers of two keep their measured table; eight lengths take
+// a measured two-stage order; any other n with a factor 3 or 5 takes the
+// fewest stages over the radices above (each stage is one pass through LDS),
+// then the smallest largest radix (fewer registers per butterfly), then
+// non-increasing radices, searched over ordered factorizations of up to 4
+// stages (n <= 512).
 __host__ __device__ constexpr Sched make_sched(int n)
+{
+    int m = n;
+    while (m % 2 == 0) m /= 2;
+    if (n == 1 || m == 1) return make_sched_pow2(n);
+    // two-stage orders measured fastest (planes + z lines, both signs) where
+    // they differ from the rule below
+    {
+        int r0 = 0, r1 = 0;
+        switch (n) {
+        case 24: r0 = 8; r1 = 3; break;
+        case 40: r0 = 5; r1 = 8; break;
+        case 48: r0 = 16; r1 = 3; break;
+        case 72: r0 = 12; r1 = 6; break;
+        case 75: r0 = 5; r1 = 15; break;
+        case 80: r0 = 8; r1 = 10; break;
+        case 108: r0 = 9; r1 = 12; break;
+        case 120: r0 = 8; r1 = 15; break;
+        default: break;
+        }
+        if (r0) return Sched{2, {r0, r1, 0, 0, 0, 0, 0, 0}};
+    }
+    Sched best{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+    int best_max = 1 << 30;
+    const int rs[11] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+    for (int stages = 1; stages <= 4 && best.count == 0; ++stages) {
+        // enumerate non-increasing radix sequences of length `stages` with product n
+        int idx[4] = {0, 0, 0, 0};
+        for (;;) {
+            long prod = 1;
+            bool ordered = true;
+            for (int i = 0; i < stages; ++i) {
+                prod *= rs[idx[i]];
+                if (i > 0 && rs[idx[i]] > rs[idx[i - 1]]) ordered = false;
+            }
+            if (ordered && prod == n) {
+                const int mx = rs[idx[0]];
+                if (mx < best_max) {
+                    best_max = mx;
+                    best.count = stages;
+                    for (int i = 0; i < stages; ++i) best.r[i] = rs[idx[i]];
+                }
+            }
+            int k = stages - 1;
+            while (k >= 0 && idx[k] == 10) { idx[k] = 0; --k; }
+            if (k < 0) break;
+            ++idx[k];
+        }
+    }
+    if (best.count) return best;
+    // not reachable for 2*3*5-smooth n <= 512; fall back to single factors
+    Sched s = make_sched_pow2(n / m * 1);
+    while (m % 3 == 0) { s.r[s.count++] = 3; m /= 3; }
+    while (m % 5 == 0) { s.r[s.count++] = 5; m /= 5; }
+    return s;
+}
+
+// Powers of two (and the power-of-two part of other lengths).
+__host__ __device__ constexpr Sched make_sched_pow2(int n)
 {
     Sched s{0, {0, 0, 0, 0, 0, 0, 0, 0}};
     if (n == 1) {
