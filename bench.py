@@ -653,13 +653,13 @@ def bench_q16(args, prec):
         t = _time(lambda: _lib.check(L.fft3d_exec_pass(inv.handle, k, src.data_ptr(), dst.data_ptr(), sh)),
                   max(10, args.steps), 3, stream)
         passes.append(t)
-    # the same step with the radix-16 stage on the vector ALUs (FFT3D_Q16_VALU=1 at plan time)
-    os.environ["FFT3D_Q16_VALU"] = "1"
-    inv_v = fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_INVERSE)
-    fwd_v = fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_FORWARD)
-    del os.environ["FFT3D_Q16_VALU"]
-    ms_valu = _time(lambda: (inv_v.exec_ptr(qa.data_ptr(), qb.data_ptr(), sh),
-                             fwd_v.exec_ptr(qb.data_ptr(), qc.data_ptr(), sh)), args.steps, args.warmup, stream)
+    # the same step with the radix-16 stage on the matrix cores (FFT3D_Q16_MFMA=1 at plan time)
+    os.environ["FFT3D_Q16_MFMA"] = "1"
+    inv_m = fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_INVERSE)
+    fwd_m = fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_FORWARD)
+    del os.environ["FFT3D_Q16_MFMA"]
+    ms_mfma = _time(lambda: (inv_m.exec_ptr(qa.data_ptr(), qb.data_ptr(), sh),
+                             fwd_m.exec_ptr(qb.data_ptr(), qc.data_ptr(), sh)), args.steps, args.warmup, stream)
     # FP32 reference path on the dequantized input, same step
     xd = fft3d.dequantize(qa, x.shape, prec)
     b32, c32 = torch.empty_like(xd), torch.empty_like(xd)
@@ -688,7 +688,7 @@ def bench_q16(args, prec):
     alg = 8.0 * n ** 3 * B + 2.0 * n * n * B
     rec = _base_record(2 * flops / (ms * 1e-3) / 1e9, "GFLOP/s", args, ms,
                        "c2c 3D FFT, 32 grids of 128^3 in scaled %s storage (per-row power-of-two exponent), inverse "
-                       "then forward, radix-16 on MFMA" % prec,
+                       "then forward, radix-16 stage on the vector ALUs (default engine)" % prec,
                        {"n": n, "batch": B, "precision": prec + "_scaled",
                         "input": "sphere-cutoff plane-wave coefficients, seeds 3000+j, quantized on the GPU"},
                        dtype="f32 arithmetic, %s storage" % prec)
@@ -699,7 +699,7 @@ def bench_q16(args, prec):
         "rel_l2_vs_fp64": {"inverse_vs_dequantized_input_max": max(e_inv), "forward_max": max(e_fwd),
                            "inverse_vs_original_fp32_input_max": max(e_orig), "grids": [0, 16, 31]},
         "fp32_same_step_ms": round(ms32, 5), "speedup_vs_fp32": round(ms32 / ms, 3),
-        "radix16_engine_ms": {"mfma": round(ms, 5), "valu": round(ms_valu, 5)},
+        "radix16_engine_ms": {"valu_default": round(ms, 5), "mfma": round(ms_mfma, 5)},
         "kernels_ms_inverse": [round(t, 5) for t in passes],
         "plans": {"inverse": inv.describe()},
         "roofline": {"bound": "hbm", "achieved": round(alg / (passes[dom] * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,

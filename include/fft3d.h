@@ -27,10 +27,12 @@
  * followed at byte offset 4 * batch * nx*ny*nz by one int8 exponent per
  * x-row ([batch][z][y], batch*nz*ny bytes).  A point's value is payload *
  * 2^exponent.  Exponents follow the rule of fft3d_quantize.  These plans need
- * nx == ny == nz with 16 | n (16, 32, 48, 64, 80, 96, 128); the radix-16
- * stage runs as a DFT-matrix product with FP16 operands and FP32
- * accumulation on the matrix cores, everything else in FP32; the
- * intermediate between the xy and z passes is stored as scaled binary16.
+ * nx == ny == nz with 16 | n (16, 32, 48, 64, 80, 96, 128); all arithmetic
+ * is FP32 (the radix-16 stage as an FP32 butterfly on the vector ALUs; with
+ * the environment variable FFT3D_Q16_MFMA=1 at plan time it runs instead as
+ * a DFT-matrix product with FP16 operands and FP32 accumulation on the
+ * matrix cores); the intermediate between the xy and z passes is stored as
+ * scaled binary16.
  *
  * Memory: every data pointer passed to an exec call is a DEVICE pointer
  * (hipMalloc / torch CUDA tensor memory) on the device the plan was created

@@ -133,7 +133,9 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
     p->precision = precision; p->direction = direction; p->device = dev; p->vol = vol;
     if (q16) {
         p->scheme = kQ16;
-        p->q16_valu = env_flag("FFT3D_Q16_VALU");
+        // radix-16 stage on the vector ALUs unless FFT3D_Q16_MFMA=1 asks for the matrix cores
+        // (the vector-ALU stage measured faster and more accurate on MI355X)
+        p->q16_valu = !env_flag("FFT3D_Q16_MFMA");
     }
     else if (large) p->scheme = kAxes;
     else if (nx == ny && ny == nz && nx <= kCubeMaxN) p->scheme = kCube;

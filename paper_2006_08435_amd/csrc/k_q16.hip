@@ -4,21 +4,50 @@
 
 namespace fft3d {
 
+// Persistent launches: as many workgroups as fit the device at once (the
+// occupancy of the kernel times the compute units), capped by the work.
+static long resident_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return cus;
+}
+
+template <class K>
+static long persistent_grid(K kernel, int threads, long work)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kernel), threads, 0) !=
+            hipSuccess ||
+        nb < 1) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    const long g = (long)nb * resident_cus();
+    return work < g ? work : g;
+}
+
 // fmt: 1 binary16, 2 bfloat16; +16 selects the vector-ALU radix-16 stage.
 template <int N, int S, int F, bool M>
 static void plane_k(const unsigned* ip, const signed char* ie, unsigned* mp, signed char* me, const float2* tw,
                     long planes, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_q16_plane<N, S, F, M>), dim3((unsigned)planes), dim3(Q16Geom<N>::T), 0, st, ip, ie, mp, me,
-                       tw);
+    const long grid = persistent_grid(&k_q16_plane<N, S, F, M>, Q16Geom<N>::T, planes);
+    hipLaunchKernelGGL((k_q16_plane<N, S, F, M>), dim3((unsigned)grid), dim3(Q16Geom<N>::T), 0, st, ip, ie, mp, me,
+                       tw, planes);
 }
 
 template <int N, int S, int F, bool M>
 static void slab_k(const unsigned* mp, const signed char* me, unsigned* op, signed char* oe, const float2* tw,
                    long slabs, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_q16_slab<N, S, F, M>), dim3((unsigned)slabs), dim3(Q16Geom<N>::T), 0, st, mp, me, op, oe,
-                       tw);
+    const long grid = persistent_grid(&k_q16_slab<N, S, F, M>, Q16Geom<N>::T, slabs);
+    hipLaunchKernelGGL((k_q16_slab<N, S, F, M>), dim3((unsigned)grid), dim3(Q16Geom<N>::T), 0, st, mp, me, op, oe,
+                       tw, slabs);
 }
 
 template <int N, int S>

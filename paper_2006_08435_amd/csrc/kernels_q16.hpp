@@ -1,5 +1,7 @@
-// Reduced-precision form: scaled 16-bit storage with FP32 arithmetic and the
-// radix-16 stage as a DFT-matrix product on the matrix cores.
+// Reduced-precision form: scaled 16-bit storage with FP32 arithmetic; the
+// radix-16 stage runs either as an FP32 butterfly on the vector ALUs (the
+// default: faster and more accurate on MI355X) or as a DFT-matrix product on
+// the matrix cores.
 //
 // Storage ("scaled16"): a buffer of R rows of C complex values holds a
 // payload of R*C 32-bit words (low half = real part, high half = imaginary
@@ -10,7 +12,7 @@
 // [2^14, 2^15).  Conversions round to nearest, ties to even.
 //
 // Transform (cubic N, 16 | N): the 1D schedule is radix 16 first, then the
-// default schedule of N / 16.  The radix-16 stage multiplies 16-point columns
+// default schedule of N / 16.  The matrix-core radix-16 stage multiplies 16-point columns
 // by the DFT matrix written as a real 32x32 matrix [[C, -sS], [sS, C]]
 // (C = cos, S = sin of 2 pi m k / 16, s = exponent sign) with
 // v_mfma_f32_16x16x32_f16: FP16 operands (each column scaled by a power of
@@ -65,33 +67,46 @@ struct Q16Geom {
     static constexpr int T = threads_for_kind<N, 1>(N);
 };
 
-// Load NR rows of N scaled16 values (row r's payload at pay + r * rstride,
-// its exponent at ex[r * estride]) and store their exact FP32 values into
-// the LDS tile (row stride RS).  One 4-byte payload word per lane and load,
-// consecutive lanes on consecutive points (coalesced loads, conflict-free
-// LDS stores); all global loads are issued before the first LDS store.
-template <int NR, int N, int RS, int T, int FMT>
-__device__ __forceinline__ void q16_load_tile(const unsigned* pay, long rstride, const signed char* ex, long estride,
-                                              float2* lds, int* lds_e, int tid)
-{
-    constexpr int UNITS = NR * N, IT = (UNITS + T - 1) / T;
+// NR rows of N scaled16 payload words held in registers (one 4-byte word
+// per lane and load, consecutive lanes on consecutive points: coalesced
+// loads, conflict-free LDS stores), plus the row exponent of row `tid`: the
+// next tile is loaded while the current one is being transformed.
+template <int NR, int N, int T>
+struct Q16Regs {
+    static constexpr int UNITS = NR * N, IT = (UNITS + T - 1) / T;
+    static_assert(NR <= T, "one exponent per thread");
     unsigned u[IT];
+    int ev;
+    // rows r at pay + r * rstride, exponents at ex[r * estride]
+    __device__ __forceinline__ void load(const unsigned* pay, long rstride, const signed char* ex, long estride,
+                                         int tid)
+    {
 #pragma unroll
-    for (int k = 0; k < IT; ++k) {
-        const int i = tid + k * T;
-        if (UNITS % T == 0 || i < UNITS) u[k] = pay[(i / N) * rstride + (i % N)];
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (UNITS % T == 0 || i < UNITS) u[k] = pay[(i / N) * rstride + (i % N)];
+        }
+        if (tid < NR) ev = ex[tid * estride];
     }
-    for (int r = tid; r < NR; r += T) lds_e[r] = ex[r * estride];
-    __syncthreads();
+    // exact FP32 values into the LDS tile (row stride RS); lds_e must hold
+    // the exponents (see put_exponent) and be visible to every thread
+    template <int RS, int FMT>
+    __device__ __forceinline__ void to_lds(float2* lds, const int* lds_e, int tid) const
+    {
 #pragma unroll
-    for (int k = 0; k < IT; ++k) {
-        const int i = tid + k * T;
-        if (UNITS % T == 0 || i < UNITS) {
-            const int r = i / N, x = i % N, e = lds_e[r];
-            lds[r * RS + x] = make_float2(ldexpf(dec16<FMT>(u[k] & 0xFFFFu), e), ldexpf(dec16<FMT>(u[k] >> 16), e));
+        for (int k = 0; k < IT; ++k) {
+            const int i = tid + k * T;
+            if (UNITS % T == 0 || i < UNITS) {
+                const int r = i / N, x = i % N, e = lds_e[r];
+                lds[r * RS + x] = make_float2(ldexpf(dec16<FMT>(u[k] & 0xFFFFu), e), ldexpf(dec16<FMT>(u[k] >> 16), e));
+            }
         }
     }
-}
+    __device__ __forceinline__ void put_exponent(int* lds_e, int tid) const
+    {
+        if (tid < NR) lds_e[tid] = ev;
+    }
+};
 
 // Requantize NR rows of N FP32 values from the LDS tile to scaled16: one
 // wave per row (lanes along the row), row maximum by a wave reduction.
@@ -209,44 +224,62 @@ __device__ __forceinline__ void q16_fft_lds(float2* lds, const float2* __restric
     if constexpr (P::stages > 4) { fft_stage_p<P, 4, S, L, T, true, true>(a, a, tw, tid); __syncthreads(); }
 }
 
-// Pass A: plane p = b * N + z.  Rows of the input (b, z, y) -> rows of the
-// FP16 intermediate (b, z, ky).
+// Pass A: planes p = b * N + z, persistent over `planes` with the next plane
+// prefetched into registers.  Rows of the input (b, z, y) -> rows of the FP16
+// intermediate (b, z, ky).
 template <int N, int S, int FMT_IN, bool MFMA>
 __global__ void __launch_bounds__(Q16Geom<N>::T)
 k_q16_plane(const unsigned* in_pay, const signed char* in_exp, unsigned* mid_pay, signed char* mid_exp,
-            const float2* __restrict__ tw)
+            const float2* __restrict__ tw, long planes)
 {
     using G = Q16Geom<N>;
     constexpr int T = G::T, RS = G::RS;
     __shared__ float2 lds[G::WORDS];
     __shared__ int lds_e[N];
     const int tid = threadIdx.x;
-    const long p = blockIdx.x;
-    q16_load_tile<N, N, RS, T, FMT_IN>(in_pay + p * N * N, N, in_exp + p * N, 1, lds, lds_e, tid);
-    __syncthreads();
-    q16_fft_lds<N, S, N, T, RS, 1, MFMA>(lds, tw, tid);   // x: lines = rows
-    q16_fft_lds<N, S, N, T, 1, RS, MFMA>(lds, tw, tid);   // y: lines = columns
-    q16_store_rows<N, N, RS, T, kFmtF16>(lds, mid_pay + p * N * N, N, mid_exp + p * N, 1, tid);
+    Q16Regs<N, N, T> regs;
+    long p = blockIdx.x;
+    if (p < planes) regs.load(in_pay + p * N * N, N, in_exp + p * N, 1, tid);
+    for (; p < planes; p += gridDim.x) {
+        regs.put_exponent(lds_e, tid);
+        __syncthreads();   // exponents visible; the previous plane is done with the tile
+        regs.template to_lds<RS, FMT_IN>(lds, lds_e, tid);
+        const long pn = p + gridDim.x;
+        if (pn < planes) regs.load(in_pay + pn * N * N, N, in_exp + pn * N, 1, tid);
+        __syncthreads();
+        q16_fft_lds<N, S, N, T, RS, 1, MFMA>(lds, tw, tid);   // x: lines = rows
+        q16_fft_lds<N, S, N, T, 1, RS, MFMA>(lds, tw, tid);   // y: lines = columns
+        q16_store_rows<N, N, RS, T, kFmtF16>(lds, mid_pay + p * N * N, N, mid_exp + p * N, 1, tid);
+    }
 }
 
-// Pass B: slab s = b * N + y; rows (b, z, y) of the intermediate for all z
-// -> rows (b, kz, y) of the output.
+// Pass B: slabs s = b * N + y, persistent likewise; rows (b, z, y) of the
+// intermediate for all z -> rows (b, kz, y) of the output.
 template <int N, int S, int FMT_OUT, bool MFMA>
 __global__ void __launch_bounds__(Q16Geom<N>::T)
 k_q16_slab(const unsigned* mid_pay, const signed char* mid_exp, unsigned* out_pay, signed char* out_exp,
-           const float2* __restrict__ tw)
+           const float2* __restrict__ tw, long slabs)
 {
     using G = Q16Geom<N>;
     constexpr int T = G::T, RS = G::RS;
     __shared__ float2 lds[G::WORDS];
     __shared__ int lds_e[N];
     const int tid = threadIdx.x;
-    const long s = blockIdx.x, b = s / N, y = s % N;
-    const long row0 = b * N * N + y;   // row index of (b, z = 0, y); rows of successive z are N apart
-    q16_load_tile<N, N, RS, T, kFmtF16>(mid_pay + row0 * N, (long)N * N, mid_exp + row0, N, lds, lds_e, tid);
-    __syncthreads();
-    q16_fft_lds<N, S, N, T, 1, RS, MFMA>(lds, tw, tid);   // z: lines = x, elements along z (LDS rows)
-    q16_store_rows<N, N, RS, T, FMT_OUT>(lds, out_pay + row0 * N, (long)N * N, out_exp + row0, N, tid);
+    Q16Regs<N, N, T> regs;
+    // row index of (b, z = 0, y); rows of successive z are N apart
+    auto row0 = [](long s) { return (s / N) * N * N + (s % N); };
+    long s = blockIdx.x;
+    if (s < slabs) regs.load(mid_pay + row0(s) * N, (long)N * N, mid_exp + row0(s), N, tid);
+    for (; s < slabs; s += gridDim.x) {
+        regs.put_exponent(lds_e, tid);
+        __syncthreads();
+        regs.template to_lds<RS, kFmtF16>(lds, lds_e, tid);
+        const long sn = s + gridDim.x;
+        if (sn < slabs) regs.load(mid_pay + row0(sn) * N, (long)N * N, mid_exp + row0(sn), N, tid);
+        __syncthreads();
+        q16_fft_lds<N, S, N, T, 1, RS, MFMA>(lds, tw, tid);   // z: lines = x, elements along z (LDS rows)
+        q16_store_rows<N, N, RS, T, FMT_OUT>(lds, out_pay + row0(s) * N, (long)N * N, out_exp + row0(s), N, tid);
+    }
 }
 
 // Standalone conversions (fft3d_quantize / fft3d_dequantize): one wave per

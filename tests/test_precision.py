@@ -99,7 +99,7 @@ def test_transform_within_bound(F, n, prec, direction):
     b = 2 if n <= 64 else 1
     x = np.stack([workloads.sphere_grid(n, 900 + n + j) for j in range(b)])
     plan, pin, ein, pout, eout = run_q16(F, x, prec, direction)
-    engine = "VALU" if os.environ.get("FFT3D_Q16_VALU") == "1" else "MFMA"   # radix-16 engine chosen at plan time
+    engine = "MFMA" if os.environ.get("FFT3D_Q16_MFMA") == "1" else "VALU"   # radix-16 engine chosen at plan time
     assert "scaled16" in plan.describe() and "radix-16 on " + engine in plan.describe()
     xin = oracle.q16_decode(pin, ein, FMT[prec])        # the input IS the 16-bit data
     got = oracle.q16_decode(pout, eout, FMT[prec])
@@ -143,14 +143,15 @@ def test_batch_32x128(F, prec):
             assert r <= TOL16, (prec, direction, j, r)
 
 
+@pytest.mark.parametrize("n", [16, 64, 128])
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
-def test_valu_engine_within_bound(F, prec, monkeypatch):
-    """The same transform with the radix-16 stage on the vector ALUs."""
-    monkeypatch.setenv("FFT3D_Q16_VALU", "1")
-    n = 64
-    x = np.stack([workloads.sphere_grid(n, 300 + j) for j in range(2)])
+def test_mfma_engine_within_bound(F, n, prec, monkeypatch):
+    """The same transform with the radix-16 stage as a DFT-matrix product on
+    the matrix cores (FFT3D_Q16_MFMA=1)."""
+    monkeypatch.setenv("FFT3D_Q16_MFMA", "1")
+    x = np.stack([workloads.sphere_grid(n, 300 + n + j) for j in range(2)])
     plan, pin, ein, pout, eout = run_q16(F, x, prec, 1)
-    assert "radix-16 on VALU" in plan.describe()
+    assert "radix-16 on MFMA" in plan.describe()
     xin = oracle.q16_decode(pin, ein, FMT[prec])
     got = oracle.q16_decode(pout, eout, FMT[prec])
     assert rel(got, oracle.fft3d(xin, 1)) <= TOL16
