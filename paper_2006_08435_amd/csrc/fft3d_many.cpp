@@ -71,10 +71,16 @@ size_t plan_lds(const ManyPlan& mp, int threads)
     return m;
 }
 
-// Apply a (threads, chunk) schedule: occupancy, grid, work list.
+// Apply a (threads, chunk) schedule: occupancy, grid, work list.  threads
+// 0 selects the grouped mode (nothing to prepare).
 int apply_schedule(fft3d_plan_s* p, int threads, int chunk)
 {
     ManyPlan& mp = p->mp;
+    if (threads == 0) {
+        mp.threads = 0;
+        mp.chunk = 1;
+        return FFT3D_OK;
+    }
     const size_t lds = plan_lds(mp, threads);
     const int per_cu = many_blocks_per_cu(threads, lds);
     if (per_cu < 1) return FFT3D_E_UNSUPPORTED;
@@ -94,6 +100,31 @@ int apply_schedule(fft3d_plan_s* p, int threads, int chunk)
     mp.grid = (int)(claims < resident ? claims : resident);
     return FFT3D_OK;
 }
+
+// Grouped mode: for each group its plane pass and its z pass, as a dense
+// plan of that group would launch them (the persistent kernel's alternative
+// when the groups are few and large).
+hipError_t launch_grouped(const fft3d_plan_s* p, const void* const* in, void* const* out, hipStream_t st)
+{
+    const ManyPlan& mp = p->mp;
+    const int cus = device_cus(p->device);
+    hipError_t e = hipSuccess;
+    for (int g = 0; g < mp.ngroups && e == hipSuccess; ++g) {
+        const int n = mp.n[g];
+        const long planes = (long)mp.batch[g] * n, resident = (long)plane_pf_blocks_per_cu(n) * cus;
+        const float2* tw = p->d_tw + mp.twoff_host[n];
+        const float2* src = static_cast<const float2*>(in[g]);
+        float2* dst = static_cast<float2*>(out[g]);
+        e = plane_pf_fn(n, p->direction)(src, dst, tw, planes, (int)(planes < resident ? planes : resident), 0,
+                                         nullptr, nullptr, n, st);
+        const long vol = (long)n * n * n;
+        const AxisMap zmap{(long)mp.batch[g] * n * n, n, n, vol, (long)n, (long)n * n};
+        if (e == hipSuccess && n > 1) e = axis_str_fn(n, p->direction)(dst, dst, tw, zmap, 0, nullptr, nullptr, 0, st);
+    }
+    return e;
+}
+
+hipError_t run_many(const fft3d_plan_s* p, const void* const* in, void* const* out, hipStream_t st);
 
 ManyArgs make_args(const fft3d_plan_s* p, const void* const* in, void* const* out)
 {
@@ -160,7 +191,7 @@ bool cache_lookup(const std::string& key, int& threads, int& chunk)
     int t = 0, c = 0;
     double ms = 0;
     if (std::sscanf(it->second.c_str(), "{\"threads\": %d, \"chunk\": %d, \"ms\": %lf}", &t, &c, &ms) != 3) return false;
-    if ((t != 512 && t != 1024) || c < 1 || c > 64) return false;
+    if ((t != 0 && t != 512 && t != 1024) || c < 1 || c > 64) return false;
     threads = t;
     chunk = c;
     return true;
@@ -206,17 +237,20 @@ int tune(fft3d_plan_s* p)
     if (rc == FFT3D_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = FFT3D_E_LAUNCH;
     double best = 1e30;
     int bt = mp.threads, bc = mp.chunk;
-    const int cand_t[] = {1024, 512};
+    // candidates: the grouped mode, then the persistent kernel's (threads, chunk)
+    const int cand_t[] = {0, 1024, 512};
     const int cand_c[] = {1, 2, 4, 8};
     for (int t : cand_t)
         for (int c : cand_c) {
             if (rc != FFT3D_OK) break;
+            if (t == 0 && c != 1) continue;
             if (apply_schedule(p, t, c) != FFT3D_OK) continue;
-            const ManyArgs a = make_args(p, (const void* const*)bufs.data(), bufs.data());
+            const void* const* ib = (const void* const*)bufs.data();
+            void* const* ob = bufs.data();
             bool ok = true;
-            for (int w = 0; w < 2 && ok; ++w) ok = launch_many(a, p->direction, t, mp.grid, mp.lds, nullptr) == hipSuccess;
+            for (int w = 0; w < 2 && ok; ++w) ok = run_many(p, ib, ob, nullptr) == hipSuccess;
             ok = ok && hipEventRecord(e0, nullptr) == hipSuccess;
-            for (int r = 0; r < 5 && ok; ++r) ok = launch_many(a, p->direction, t, mp.grid, mp.lds, nullptr) == hipSuccess;
+            for (int r = 0; r < 5 && ok; ++r) ok = run_many(p, ib, ob, nullptr) == hipSuccess;
             ok = ok && hipEventRecord(e1, nullptr) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
             float ms = 0.f;
             if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms / 5 < best) {
@@ -238,6 +272,13 @@ int tune(fft3d_plan_s* p)
         cache_store(cache_key(p), bt, bc, best);
     }
     return rc;
+}
+
+hipError_t run_many(const fft3d_plan_s* p, const void* const* in, void* const* out, hipStream_t st)
+{
+    if (p->mp.threads == 0) return launch_grouped(p, in, out, st);
+    const ManyArgs a = make_args(p, in, out);
+    return launch_many(a, p->direction, p->mp.threads, p->mp.grid, p->mp.lds, st);
 }
 
 void free_plan(fft3d_plan_s* p)
@@ -305,6 +346,7 @@ fft3d_plan_t fft3d_plan_many(int count, const int* nx, const int* ny, const int*
         for (int h = 0; h < g; ++h) seen = seen || mp.n[h] == nx[g];
         if (!seen) {
             twoff[nx[g]] = (int)tab.size();
+            mp.twoff_host[nx[g]] = (int)tab.size();
             const std::vector<float2> t = twiddles(nx[g], direction);
             tab.insert(tab.end(), t.begin(), t.end());
             if (tab.size() % 2) tab.push_back(make_float2(0.f, 0.f));
@@ -352,9 +394,7 @@ int fft3d_exec_many(fft3d_plan_t p, const void* const* in, void* const* out, fft
         if (!in[g] || !out[g]) return FFT3D_E_INVALID_ARG;
         if (((uintptr_t)in[g] % 16) || ((uintptr_t)out[g] % 16)) return FFT3D_E_ALIGNMENT;
     }
-    const ManyArgs a = make_args(p, in, out);
-    if (launch_many(a, p->direction, p->mp.threads, p->mp.grid, p->mp.lds, reinterpret_cast<hipStream_t>(stream)) !=
-        hipSuccess) {
+    if (run_many(p, in, out, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) {
         (void)hipGetLastError();
         return FFT3D_E_LAUNCH;
     }
@@ -363,7 +403,8 @@ int fft3d_exec_many(fft3d_plan_t p, const void* const* in, void* const* out, fft
 
 int fft3d_plan_set_schedule(fft3d_plan_t p, int threads, int chunk)
 {
-    if (!p || !p->many || (threads != 512 && threads != 1024) || chunk < 1 || chunk > 64) return FFT3D_E_INVALID_ARG;
+    if (!p || !p->many || (threads != 0 && threads != 512 && threads != 1024) || chunk < 1 || chunk > 64)
+        return FFT3D_E_INVALID_ARG;
     return apply_schedule(p, threads, chunk);
 }
 
@@ -382,9 +423,14 @@ int many_describe(fft3d_plan_t p, char* buf, size_t len)
     std::ostringstream d;
     d << "many groups=";
     for (int g = 0; g < p->mp.ngroups; ++g) d << (g ? "," : "") << p->mp.n[g] << "^3x" << p->mp.batch[g];
-    d << " threads=" << p->mp.threads << " chunk=" << p->mp.chunk << " workgroups=" << p->mp.grid
-      << " lds=" << p->mp.lds << " items=" << p->mp.nitems << (p->mp.tuned ? " tuned" : " default")
-      << (p->direction < 0 ? " forward" : " inverse") << " kernels=k_many";
+    if (p->mp.threads == 0) {
+        d << " mode=grouped" << (p->mp.tuned ? " tuned" : " default") << (p->direction < 0 ? " forward" : " inverse")
+          << " kernels=k_plane_pf,k_axis_str per group";
+    } else {
+        d << " mode=persistent threads=" << p->mp.threads << " chunk=" << p->mp.chunk << " workgroups=" << p->mp.grid
+          << " lds=" << p->mp.lds << " items=" << p->mp.nitems << (p->mp.tuned ? " tuned" : " default")
+          << (p->direction < 0 ? " forward" : " inverse") << " kernels=k_many";
+    }
     const std::string s = d.str();
     if (buf && len) {
         std::strncpy(buf, s.c_str(), len - 1);

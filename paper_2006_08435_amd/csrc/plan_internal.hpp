@@ -43,8 +43,9 @@ struct ManyPlan {
     long nitems = 0;
     long items_cap = 0;
     int* d_twoff = nullptr;
-    int threads = 1024;
+    int threads = 1024;   // 0: grouped mode (two plain passes per group) instead of the persistent kernel
     int chunk = 2;
+    int twoff_host[129] = {};   // offset of the length-n table in the plan's twiddles
     int grid = 1;
     size_t lds = 0;
     bool tuned = false;

@@ -76,6 +76,23 @@ def test_every_schedule_gives_identical_results(F):
     assert _lib.lib().fft3d_plan_check(plan.handle) == 0
 
 
+def test_grouped_mode(F):
+    """threads = 0: each group's plane and z passes as plain launches; same
+    transform as the persistent kernel (to rounding: other kernels)."""
+    groups = [(64, 3), (72, 1), (48, 2), (128, 1)]
+    xs = inputs(groups, 7)
+    plan = F.PlanMany(groups, -1)
+    plan.set_schedule(1024, 2)
+    pers = run(plan, xs)
+    plan.set_schedule(0, 1)
+    assert "mode=grouped" in plan.describe()
+    got = run(plan, xs)
+    for (n, b), x, y, z in zip(groups, xs, got, pers):
+        for j in range(b):
+            assert rel(y[j], oracle.fft3d(x[j].astype(np.complex128), -1)) <= TOL
+        assert rel(y, z) <= 1e-6
+
+
 def test_matches_plain_per_grid_execs(F):
     groups = [(96, 2), (60, 3)]
     xs = inputs(groups, 21)
@@ -101,10 +118,12 @@ def test_inplace_and_repeat(F):
         assert np.array_equal(a, b.cpu().numpy())
 
 
-def test_graph_capture_replays_match_eager(F):
+@pytest.mark.parametrize("threads,chunk", [(1024, 2), (0, 1)])
+def test_graph_capture_replays_match_eager(F, threads, chunk):
     groups = [(64, 4), (80, 1), (36, 2)]
     xs = inputs(groups, 41)
     plan = F.PlanMany(groups, -1)
+    plan.set_schedule(threads, chunk)
     ins = [torch.from_numpy(x).cuda() for x in xs]
     eager = [o.clone() for o in plan.exec(ins)]
     outs = [torch.empty_like(t) for t in ins]
@@ -135,17 +154,23 @@ def test_tuner_and_cache(F, tmp_path, monkeypatch):
     assert "tuned" in p1.describe()
     d = json.loads(cache.read_text())
     (key, val), = d.items()
-    assert val["threads"] in (512, 1024) and 1 <= val["chunk"] <= 8 and val["ms"] > 0
+    assert val["threads"] in (0, 512, 1024) and 1 <= val["chunk"] <= 8 and val["ms"] > 0
     monkeypatch.delenv("FFT3D_TUNE")
     p2 = F.PlanMany(groups, -1)            # read back from the cache
     assert "tuned" in p2.describe()
-    assert "threads=%d chunk=%d" % (val["threads"], val["chunk"]) in p2.describe()
+    if val["threads"] == 0:
+        assert "mode=grouped" in p2.describe()
+    else:
+        assert "threads=%d chunk=%d" % (val["threads"], val["chunk"]) in p2.describe()
     cache.write_text("{ this is not json")  # a corrupt cache falls back to the default
     p3 = F.PlanMany(groups, -1)
     assert "default" in p3.describe()
     xs = inputs(groups, 51)
     for a, b in zip(run(p1, xs), run(p3, xs)):
-        assert np.array_equal(a, b)
+        if val["threads"] == 0:             # other kernels: equal to rounding
+            assert rel(a, b) <= 1e-6
+        else:
+            assert np.array_equal(a, b)
 
 
 def test_mixed_grid_workload(F):
