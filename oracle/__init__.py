@@ -82,6 +82,7 @@ def _bind(lib):
     lib.oracle_q16_decode.argtypes = [ci, ctypes.c_long, ci, u16, i8, dp]
     lib.oracle_energy.argtypes = [ci, ci, ci, ci, dp, dp, dp, dp, dp]
     lib.oracle_apply_potential.argtypes = [ci, ci, ci, ci, dp, dp, dp]
+    lib.oracle_density.argtypes = [ci, ci, ci, ci, dp, dp, dp]
     lib.oracle_r2c3d.argtypes = [ci, ci, ci, ci, dp, dp]
     lib.oracle_c2r3d.argtypes = [ci, ci, ci, ci, dp, dp]
     return lib
@@ -190,6 +191,20 @@ def apply_potential(c, V) -> np.ndarray:
     _check(lib.oracle_apply_potential(nx, ny, nz, b, _ptr(x, ctypes.c_double), _ptr(v, ctypes.c_double),
                                       _ptr(out, ctypes.c_double)))
     return out[0] if squeeze else out
+
+
+def density(c, occ) -> np.ndarray:
+    """rho = sum_n occ[n] |inverse(c_n)|^2, a real [z, y, x] grid."""
+    lib = _load()
+    x, _ = _shape3(c)
+    b, nz, ny, nx = x.shape
+    f = np.ascontiguousarray(occ, dtype=np.float64).ravel()
+    if f.size != b:
+        raise ValueError("one occupation per orbital")
+    rho = np.empty((nz, ny, nx), np.float64)
+    _check(lib.oracle_density(nx, ny, nz, b, _ptr(x, ctypes.c_double), _ptr(f, ctypes.c_double),
+                              _ptr(rho, ctypes.c_double)))
+    return rho
 
 
 def r2c3d(f) -> np.ndarray:

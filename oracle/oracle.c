@@ -516,6 +516,32 @@ int oracle_apply_potential(int nx, int ny, int nz, int batch, const double *c,
     return err;
 }
 
+/*
+ * The electron density of a plane-wave code from its orbital coefficients:
+ * rho(r) = sum_n f_n |psi_n(r)|^2 with psi_n the unnormalised inverse
+ * transform (sign +1) of c_n and f_n the occupation of orbital n.  rho is a
+ * real [z][y][x] grid.
+ */
+int oracle_density(int nx, int ny, int nz, int batch, const double *c,
+                   const double *occ, double *rho)
+{
+    const long vol = (long)nx * ny * nz;
+    const int inverse_sign = +1;
+    double *p = malloc(sizeof(double) * 2 * vol * batch);
+    if (!p) return -4;
+    int err = oracle_fft3d(nx, ny, nz, batch, inverse_sign, c, p);
+    if (!err) {
+        for (long i = 0; i < vol; ++i) rho[i] = 0.0;
+        for (int b = 0; b < batch; ++b)
+            for (long i = 0; i < vol; ++i) {
+                const double re = p[2 * (b * vol + i)], im = p[2 * (b * vol + i) + 1];
+                rho[i] += occ[b] * (re * re + im * im);
+            }
+    }
+    free(p);
+    return err;
+}
+
 int oracle_energy(int nx, int ny, int nz, int batch, const double *c,
                   const double *V, double *E, double *psi, double *grad)
 {

@@ -328,6 +328,23 @@ def pin_apply_potential():
     assert rel(H, grad / 2) < 1e-13
 
 
+def pin_density():
+    """rho = sum f_n |psi_n|^2: numpy witness, the integral sum_r rho =
+    N^3 sum_n f_n sum_G |c_n|^2 (unnormalised inverse), one plane wave."""
+    nx, ny, nz, b = 6, 5, 4, 3
+    c = rand_grid((b, nz, ny, nx), 600)
+    f = np.array([2.0, 1.5, 0.25])
+    vol = nx * ny * nz
+    rho = oracle.density(c, f)
+    psi = np.fft.ifftn(c, axes=(-3, -2, -1)) * vol
+    assert np.max(np.abs(rho - np.einsum("b,bzyx->zyx", f, np.abs(psi) ** 2))) < 1e-10 * np.max(rho)
+    total = vol * float(np.sum(f[:, None, None, None] * np.abs(c) ** 2))
+    assert abs(rho.sum() - total) < 1e-10 * total
+    one = np.zeros((1, nz, ny, nx), np.complex128)
+    one[0, 1, 2, 3] = 2.0 - 1.0j                 # |psi| = |c| everywhere
+    assert np.allclose(oracle.density(one, [0.5]), 0.5 * 5.0, rtol=1e-14, atol=0)
+
+
 ALL_PINS = [pin_golden, pin_closed_forms, pin_naive_vs_numpy, pin_fft_vs_naive,
             pin_fft_vs_numpy, pin_invariants, pin_fp16_rounding, pin_bf16_rounding,
-            pin_q16_rule, pin_energy, pin_real, pin_apply_potential]
+            pin_q16_rule, pin_energy, pin_real, pin_apply_potential, pin_density]

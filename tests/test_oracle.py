@@ -67,3 +67,7 @@ def test_real_transforms():
 
 def test_apply_potential():
     P.pin_apply_potential()
+
+
+def test_density():
+    P.pin_density()

@@ -39,6 +39,10 @@ MUTANTS = {
                                  "oracle_fft3d(nx, ny, nz, batch, forward, c, p);"),
     "apply skips V imag": ("                p[2 * (b * vol + i) + 1] *= V[i];\n            }\n        err = oracle_fft3d(nx, ny, nz, batch, forward, p, out);",
                            "            }\n        err = oracle_fft3d(nx, ny, nz, batch, forward, p, out);"),
+    "density uses forward": ("oracle_fft3d(nx, ny, nz, batch, inverse_sign, c, p);",
+                             "oracle_fft3d(nx, ny, nz, batch, -inverse_sign, c, p);"),
+    "density drops occupation": ("rho[i] += occ[b] * (re * re + im * im);", "rho[i] += (re * re + im * im);"),
+    "density keeps last orbital": ("rho[i] += occ[b] * (re * re + im * im);", "rho[i] = occ[b] * (re * re + im * im);"),
     "r2c wrong half": ("out[2 * (r * h + k)] = full[2 * (r * nx + k)];",
                        "out[2 * (r * h + k)] = full[2 * (r * nx + (nx - k) % nx)];"),
 }
