@@ -378,6 +378,11 @@ def bench_energy(args):
                                            0, sh))
 
     apply_ms = _time(lambda: apply(plan), args.steps, args.warmup, stream)
+    occ = torch.full((B,), 2.0, dtype=torch.float32, device="cuda")
+    rho = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+    dwork = torch.empty_like(ct)
+    density_ms = _time(lambda: plan.density(ct, occ, rho=rho, work=dwork, stream=stream), args.steps, args.warmup,
+                       stream)
     cplan = fft3d.Plan(n, n, n, B, "fp32", fft3d.FFT3D_INVERSE)
     cplan.set_cutoff((n / 4.0) ** 2)
     apply_cut_ms = _time(lambda: apply(cplan), args.steps, args.warmup, stream)
@@ -412,7 +417,8 @@ def bench_energy(args):
         "times_ms": {"energy_fwd": round(fwd_ms, 4), "fwd_plus_bwd_saved_psi": round(both_saved, 4),
                      "fwd_plus_bwd_recompute_psi": round(both_recomp, 4),
                      "apply_potential_with_E": round(apply_ms, 4),
-                     "apply_potential_with_E_cutoff": round(apply_cut_ms, 4)},
+                     "apply_potential_with_E_cutoff": round(apply_cut_ms, 4),
+                     "density_128_orbitals": round(density_ms, 4)},
         "apply_potential": {"rel_l2_orbital0": float(np.linalg.norm(h0 - Hc_ref) / np.linalg.norm(Hc_ref)),
                             "rel_l2_orbital0_inside_sphere_cutoff":
                                 float(np.linalg.norm(hc0[msk] - Hc_ref[msk]) / np.linalg.norm(Hc_ref[msk])),

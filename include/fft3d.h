@@ -337,6 +337,25 @@ int fft3d_energy_fwd(fft3d_plan_t plan, const void *c, const float *V, void *psi
  */
 int fft3d_apply_potential(fft3d_plan_t plan, const void *c, const float *V, void *out, double *E_dev,
                           const double *scale_dev, fft3d_stream_t stream);
+
+/*
+ * Electron density from orbital coefficients, the real-space product that
+ * follows the inverse transforms of Section I's plane-wave operators:
+ * rho(r) = sum_n occ[n] |psi_n(r)|^2, psi_n the unnormalised inverse
+ * transform (sign +1) of c_n, for the plan's `batch` orbitals.  occ: device
+ * float[batch]; rho: device float [nz][ny][nx] (written, not accumulated);
+ * work: device buffer of the size of c (the xy-transformed orbitals; may
+ * equal c, which is then overwritten).  Two passes: the inverse xy planes
+ * into `work`, then one kernel per group of z-lines that runs the inverse
+ * z transform of every orbital in turn and sums occ |psi|^2 in registers
+ * (FP32, orbital order: deterministic), so psi is never stored.  With a
+ * cutoff on the plan, c must vanish outside the sphere and the pruned plane
+ * pass is used.  Plans as for the energy entry points; returns the same
+ * codes (FFT3D_E_ALIGNMENT: c / work not 16-byte, occ / rho not 4-byte
+ * aligned).
+ */
+int fft3d_density(fft3d_plan_t plan, const void *c, const float *occ, float *rho, void *work,
+                  fft3d_stream_t stream);
 int fft3d_energy_bwd(fft3d_plan_t plan, const void *c_or_psi, int have_psi, const float *V, const double *gE_dev,
                      void *grad_c, fft3d_stream_t stream);
 

@@ -127,6 +127,21 @@ class Plan:
                                                     ptr(scale), _stream_handle(stream)), "fft3d_apply_potential")
         return out
 
+    def density(self, c, occ, rho=None, work=None, stream=None):
+        """rho = sum_n occ[n] |inverse(c_n)|^2 (``fft3d_density``); work
+        defaults to a fresh buffer (c is left intact)."""
+        torch = _torch()
+        if rho is None:
+            rho = torch.empty(self.shape[1:], dtype=torch.float32, device=c.device)
+        if work is None:
+            work = torch.empty_like(c)
+        for t in (c, occ, rho, work):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("tensors must be contiguous device tensors")
+        _lib.check(_lib.lib().fft3d_density(self._h, c.data_ptr(), occ.data_ptr(), rho.data_ptr(), work.data_ptr(),
+                                            _stream_handle(stream)), "fft3d_density")
+        return rho
+
     def exec_ptr(self, in_ptr: int, out_ptr: int, stream_handle: int) -> None:
         _lib.check(_lib.lib().fft3d_exec(self._h, in_ptr, out_ptr, stream_handle), "fft3d_exec")
 

@@ -44,6 +44,7 @@ SIGNATURES = {
     "fft3d_plan_set_cutoff": (_ci, [_vp, ctypes.c_double]),
     "fft3d_plan_real": (_vp, [_ci, _ci, _ci, _ci, _ci]),
     "fft3d_apply_potential": (_ci, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fft3d_density": (_ci, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "fft3d_real_bytes": (ctypes.c_size_t, [_vp]),
     "fft3d_plan_sphere_points": (ctypes.c_longlong, [_vp]),
     "fft3d_sphere_pack": (_ci, [_vp, _vp, _vp, _vp]),

@@ -576,6 +576,41 @@ int fft3d_apply_potential(fft3d_plan_t p, const void* c, const float* V, void* o
     return FFT3D_OK;
 }
 
+int fft3d_density(fft3d_plan_t p, const void* c, const float* occ, float* rho, void* work, fft3d_stream_t stream)
+{
+    if (!p || !c || !occ || !rho || !work) return FFT3D_E_INVALID_ARG;
+    if (((uintptr_t)c % 16) || ((uintptr_t)work % 16) || ((uintptr_t)rho % 4) || ((uintptr_t)occ % 4))
+        return FFT3D_E_ALIGNMENT;
+    if (p->many || p->real || p->precision != FFT3D_FP32 || p->nx != p->ny || !p->partials)
+        return FFT3D_E_UNSUPPORTED;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int n = p->nx, nz = p->nz;
+    const bool inv_plan = p->direction == FFT3D_INVERSE;
+    const float2* twx = p->d_tw + (inv_plan ? p->tw_x : p->tw_rx);
+    const float2* twz = p->d_tw + (inv_plan ? p->tw_z : p->tw_rz);
+    const float2* src = static_cast<const float2*>(c);
+    float2* w = static_cast<float2*>(work);
+    hipError_t e;
+    const bool cut = p->cut_r2 > 0;
+    if (cut) {
+        const long planes = (long)p->batch * p->n_zlist;
+        const int grid = (int)(planes < p->pf_grid ? planes : p->pf_grid);
+        e = plane_pruned_fn(n, FFT3D_INVERSE)(src, w, twx, planes, grid, p->d_zlist, p->n_zlist, nz, p->cut_r2,
+                                              nullptr, 0, st);
+    } else {
+        e = plane_pf_fn(n, FFT3D_INVERSE)(src, w, twx, (long)p->batch * nz, p->pf_grid, 0, nullptr, nullptr, nz, st);
+    }
+    // the z-lines of one grid: (y, x) pairs, elements along z
+    const AxisMap zmap{(long)p->ny * n, n, p->ny, p->vol, (long)n, (long)n * p->ny};
+    if (e == hipSuccess)
+        e = axis_density_fn(nz)(w, twz, zmap, p->batch, p->vol, occ, rho, cut ? p->cut_r2 : 0.0, cut ? 1 : 0, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
 int fft3d_energy_bwd(fft3d_plan_t p, const void* c_or_psi, int have_psi, const float* V, const double* gE_dev,
                      void* grad_c, fft3d_stream_t stream)
 {

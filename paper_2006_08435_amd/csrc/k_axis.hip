@@ -103,6 +103,34 @@ HlocFn axis_hloc_fn(int n)
     }
 }
 
+constexpr int kDensityLines = 32;
+
+template <int N>
+static hipError_t launch_density(const float2* buf, const float2* tw, const AxisMap& m, int batch, long vol,
+                                 const float* occ, float* rho, double R2, int mode, hipStream_t st)
+{
+    const long blocks = (m.lines + kDensityLines - 1) / kDensityLines;
+    if (mode)
+        hipLaunchKernelGGL((k_axis_density<N, kDensityLines, 1>), dim3((unsigned)blocks),
+                           dim3(AxisGeom<N, kDensityLines>::T), 0, st, buf, tw, m, batch, vol, occ, rho, R2);
+    else
+        hipLaunchKernelGGL((k_axis_density<N, kDensityLines, 0>), dim3((unsigned)blocks),
+                           dim3(AxisGeom<N, kDensityLines>::T), 0, st, buf, tw, m, batch, vol, occ, rho, R2);
+    return hipGetLastError();
+}
+
+#define FFT3D_DENSITY_CASE(n)                                                  \
+    case n:                                                                    \
+        return &launch_density<n>;
+
+DensityFn axis_density_fn(int n)
+{
+    switch (n) {
+        FFT3D_FOR_EACH_SIZE(FFT3D_DENSITY_CASE)
+    default: return nullptr;
+    }
+}
+
 hipError_t launch_sphere_copy(bool pack, const float2* src, float2* dst, const SphereRow* rows, long npts, int nx,
                               long nyz, long total, hipStream_t st)
 {

@@ -1067,6 +1067,101 @@ k_axis_hloc(float2* buf, const float2* __restrict__ tw_inv, const float2* __rest
     }
 }
 
+// Density epilogue of the inverse transform: rho(r) = sum_b occ[b]
+// |psi_b(r)|^2, psi_b the inverse z-transform of orbital b of `buf` (already
+// transformed along x and y; orbitals `vol` apart).  Each workgroup owns L
+// adjacent z-lines of the grid (map: the lines of ONE grid) and loops over
+// the orbitals: stage 0 from HBM into LDS, the other stages in LDS, then each
+// thread adds occ[b] |psi|^2 at its fixed points in registers (FP32 FMA, in
+// orbital order: deterministic).  psi is never stored; rho ([z][y][x] real)
+// is written once.  MODE 1 (cutoff R2): loads only of the planes with
+// Gz^2 < R2 (the others were not written by the pruned plane pass).
+template <int N, int L, int MODE>
+__global__ void __launch_bounds__((AxisGeom<N, L>::T))
+k_axis_density(const float2* buf, const float2* __restrict__ tw, AxisMap m, int batch, long vol,
+               const float* __restrict__ occ, float* __restrict__ rho, double R2)
+{
+    using G = AxisGeom<N, L>;
+    using P = Plan1D<N>;
+    constexpr int T = G::T;
+    static_assert(T % L == 0, "each thread keeps one line");
+    constexpr int PER = (N * L + T - 1) / T;   // points per thread
+    // stage 0 (radix R0, no twiddles) is split into its loads, issued one
+    // orbital ahead into registers, and its butterflies
+    constexpr int R0 = P::radix(0), M0 = N / R0, NB0 = L * M0, IT0 = (NB0 + T - 1) / T;
+    __shared__ float2 lds[G::WORDS];
+    const int tid = threadIdx.x;
+    const long l0 = (long)blockIdx.x * L;
+    const int myline = tid % L;
+    const long li = l0 + myline;
+    const int valid = (int)((m.lines - l0) < L ? (m.lines - l0) : L);
+    long gbase = 0;
+    if (li < m.lines) {
+        const long o = li / m.nx;
+        const long x = li - o * m.nx;
+        gbase = (o / m.odiv) * m.shi + (o % m.odiv) * m.slo + x;
+    }
+    float2 pre[IT0][R0];
+    auto load0 = [&](int b) {
+        const float2* src = buf + (long)b * vol + gbase;
+#pragma unroll
+        for (int it = 0; it < IT0; ++it) {
+            const int bb = tid + it * T, j = bb / L;
+            if ((NB0 % T == 0 || bb < NB0) && myline < valid) {
+#pragma unroll
+                for (int q = 0; q < R0; ++q) {
+                    const int e = j + q * M0;
+                    if constexpr (MODE == 1) {
+                        const int g = signed_freq(e, N);
+                        pre[it][q] = (double)(g * g) < R2 ? src[(long)e * m.es] : make_float2(0.f, 0.f);
+                    } else {
+                        pre[it][q] = src[(long)e * m.es];
+                    }
+                }
+            }
+        }
+    };
+    float acc[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) acc[k] = 0.f;
+    const LdsAcc<1, G::LP> a{lds};
+    if (batch > 0) load0(0);
+    for (int b = 0; b < batch; ++b) {
+#pragma unroll
+        for (int it = 0; it < IT0; ++it) {
+            const int bb = tid + it * T, j = bb / L;
+            if ((NB0 % T == 0 || bb < NB0) && myline < valid) {
+                dft<R0, 1>(pre[it]);
+#pragma unroll
+                for (int q = 0; q < R0; ++q) lds[(j * R0 + q) * G::LP + myline] = pre[it][q];
+            }
+        }
+        __syncthreads();
+        if (b + 1 < batch) load0(b + 1);
+        if constexpr (P::stages > 1) {
+            run_tail<N, 1, L, T, 1, true>(a, a, tw, tid, valid);
+            __syncthreads();
+        }
+        const float f = occ[b];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + k * T;
+            if ((N * L) % T == 0 || i < N * L) {
+                const float2 p = lds[(i / L) * G::LP + myline];
+                acc[k] = fmaf(f, fmaf(p.x, p.x, p.y * p.y), acc[k]);
+            }
+        }
+        __syncthreads();   // the next orbital's stage 0 overwrites the tile
+    }
+    if (myline < valid) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + k * T;
+            if ((N * L) % T == 0 || i < N * L) rho[gbase + (long)(i / L) * m.es] = acc[k];
+        }
+    }
+}
+
 template <int N, int L>
 struct RowGeom {
     static constexpr int RS = odd_stride(N);

@@ -63,6 +63,11 @@ using HlocFn = hipError_t (*)(float2* buf, const float2* tw_inv, const float2* t
                               const float* V, const double* scale, float mult, double* partials, long vol, double R2,
                               int mode, hipStream_t st);
 HlocFn axis_hloc_fn(int n);
+// Density epilogue (see k_axis_density): m maps the z-lines of ONE grid,
+// orbitals are `vol` apart in buf; mode 1 = cutoff R2.
+using DensityFn = hipError_t (*)(const float2* buf, const float2* tw, const AxisMap& m, int batch, long vol,
+                                 const float* occ, float* rho, double R2, int mode, hipStream_t st);
+DensityFn axis_density_fn(int n);
 AxisStrPrunedFn axis_str_pruned_fn(int n, int sign);
 int plane_pf_blocks_per_cu(int n);
 AxisStrFn axis_str_fn(int n, int sign);

@@ -77,6 +77,7 @@ def test_null_handles():
     assert lib.fft3d_exec_packed(None, None, None, None) == -1
     assert lib.fft3d_real_bytes(None) == 0
     assert lib.fft3d_apply_potential(None, None, None, None, None, None, None) == -1
+    assert lib.fft3d_density(None, None, None, None, None, None) == -1
 
 
 def test_strerror_covers_codes():
