@@ -535,8 +535,8 @@ def bench_pruned(args):
     pk = [k for k in pass_bytes]
     dom = max(pk, key=lambda k: times[k])
     achieved = pass_bytes[dom] / (times[dom] * 1e-3) / 1e9
-    kern = {"inverse_pass0": "k_plane_pruned<128, 1, false, false>", "inverse_pass1": "k_axis_str<128, 1, 64, false, 1>",
-            "forward_pass0": "k_plane_pruned<128, -1, true, false>",
+    kern = {"inverse_pass0": "k_plane_pruned<128, 1, 0, false>", "inverse_pass1": "k_axis_str<128, 1, 64, false, 1>",
+            "forward_pass0": "k_plane_pruned<128, -1, 1, false>",
             "forward_pass1": "k_axis_str<128, -1, 64, false, 2>"}
     rec.update({
         "times_ms": dict({"pruned_step": round(pruned_ms, 4), "dense_step": round(dense_ms, 4),
@@ -719,7 +719,9 @@ def bench_q16(args, prec):
         "plans": {"inverse": inv.describe()},
         "roofline": {"bound": "hbm", "achieved": round(alg / (passes[dom] * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(alg / (passes[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": ["k_q16_plane", "k_q16_slab"][dom] + "<128,1>",
+                     "traffic": measured_traffic(args.workload, "%s<128, 1, %d, false>" % (
+                         ["k_q16_plane", "k_q16_slab"][dom], 1 if prec == "fp16" else 2)),
+                     "kernel": ["k_q16_plane", "k_q16_slab"][dom] + "<128,1>",
                      "ms_per_launch": round(passes[dom], 5)},
         "cpu_baseline": None,
         "source_hash": source_hash(),
