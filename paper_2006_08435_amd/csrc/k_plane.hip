@@ -11,16 +11,29 @@ static hipError_t launch_plane(const float2* in, float2* out, const float2* tw, 
     return hipGetLastError();
 }
 
+// Streaming plane accesses pay on batches that do not stay in the caches
+// between passes; below this many bytes per pass (a single 128^3 grid is
+// 16 MB) the default policy is faster.
+constexpr long kStreamMinBytes = 32L << 20;
+
 template <int N, int S>
 static hipError_t launch_plane_pf(const float2* in, float2* out, const float2* tw, long planes, int grid, int scale,
                                   const float* V, const double* gE, int nz, hipStream_t st)
 {
+    const dim3 g((unsigned)grid), b(PlaneGeom<N>::T);
+    if constexpr (stream_plane(N)) {
+        if (planes * N * N * (long)sizeof(float2) >= kStreamMinBytes) {
+            if (scale)
+                hipLaunchKernelGGL((k_plane_pf<N, S, true, true>), g, b, 0, st, in, out, tw, planes, V, gE, nz);
+            else
+                hipLaunchKernelGGL((k_plane_pf<N, S, false, true>), g, b, 0, st, in, out, tw, planes, V, gE, nz);
+            return hipGetLastError();
+        }
+    }
     if (scale)
-        hipLaunchKernelGGL((k_plane_pf<N, S, true>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out, tw,
-                           planes, V, gE, nz);
+        hipLaunchKernelGGL((k_plane_pf<N, S, true>), g, b, 0, st, in, out, tw, planes, V, gE, nz);
     else
-        hipLaunchKernelGGL((k_plane_pf<N, S, false>), dim3((unsigned)grid), dim3(PlaneGeom<N>::T), 0, st, in, out, tw,
-                           planes, V, gE, nz);
+        hipLaunchKernelGGL((k_plane_pf<N, S, false>), g, b, 0, st, in, out, tw, planes, V, gE, nz);
     return hipGetLastError();
 }
 

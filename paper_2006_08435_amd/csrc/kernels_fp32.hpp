@@ -118,8 +118,9 @@ __device__ __forceinline__ void tile_to_lds(const float2* g, float2* lds, int ti
 }
 
 // The same copy split in two halves so the global loads of the next tile can
-// be in flight while the current tile is being transformed.
-template <int ROWS, int ROW, int T>
+// be in flight while the current tile is being transformed.  NT: load()
+// streams (ld_stream).
+template <int ROWS, int ROW, int T, bool NT = false>
 struct TileRegs {
     static constexpr bool PAIRS = ROW % 2 == 0;
     static constexpr int UNITS = PAIRS ? ROWS * ROW / 2 : ROWS * ROW;
@@ -133,7 +134,19 @@ struct TileRegs {
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
             const int i = tid + k * T;
-            if (UNITS % T == 0 || i < UNITS) r[k] = gu[i];
+            if (UNITS % T == 0 || i < UNITS) {
+                if constexpr (NT) {
+                    if constexpr (PAIRS) {
+                        typedef float f4v __attribute__((ext_vector_type(4)));
+                        const f4v t = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(gu + i));
+                        r[k] = make_float4(t.x, t.y, t.z, t.w);
+                    } else {
+                        r[k] = ld_stream(reinterpret_cast<const float2*>(gu + i));
+                    }
+                } else {
+                    r[k] = gu[i];
+                }
+            }
         }
     }
     // Load with a row predicate: rows for which row_ok(row) is false are not
@@ -299,14 +312,15 @@ struct PlaneGeom {
 };
 
 // Global accessor for the y pass's final store: line = x, element = y.
-// COH: device-coherent (write-through) stores.
-template <int N, bool COH = false>
+// COH: device-coherent (write-through) stores; NT: streaming stores.
+template <int N, bool COH = false, bool NT = false>
 struct PlaneColOut {
     float2* p;
     __device__ __forceinline__ float2 load(int, int) const { return float2{}; }
     __device__ __forceinline__ void store(int x, int y, float2 v) const
     {
         if constexpr (COH) store_coherent(p + y * N + x, v);
+        else if constexpr (NT) st_stream(p + y * N + x, v);
         else p[y * N + x] = v;
     }
 };
@@ -344,7 +358,8 @@ k_plane(const float2* in, float2* out, const float2* __restrict__ tw)
 // SCALE: every input value at grid position r is first multiplied by the real
 // factor 2 * gE[0] * V[r] (V: one [nz][N][N] grid shared by the batch) -- the
 // prologue of the energy gradient.
-template <int N, int S, bool SCALE = false>
+// NT: streaming plane loads and stores (see stream_plane).
+template <int N, int S, bool SCALE = false, bool NT = false>
 __global__ void __launch_bounds__(PlaneGeom<N>::T)
 k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long planes, const float* __restrict__ V,
            const double* __restrict__ gE, int nz)
@@ -352,7 +367,7 @@ k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long pl
     constexpr int T = PlaneGeom<N>::T, RS = PlaneGeom<N>::RS;
     __shared__ float2 lds[PlaneGeom<N>::WORDS];
     const int tid = threadIdx.x;
-    TileRegs<N, N, T> regs;
+    TileRegs<N, N, T, NT> regs;
     FactorRegs<N, N, T> vr;
     float scale = 0.f;
     if constexpr (SCALE) scale = (float)(2.0 * gE[0]);
@@ -372,7 +387,7 @@ k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long pl
         }
         fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
         const LdsAcc<1, RS> col{lds};
-        const PlaneColOut<N> dst{out + p * N * N};
+        const PlaneColOut<N, false, NT> dst{out + p * N * N};
         run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
         __syncthreads();
     }
@@ -487,7 +502,7 @@ k_plane_pruned(const float2* in, float2* out, const float2* __restrict__ tw, lon
     constexpr int T = PlaneGeom<N>::T, RS = PlaneGeom<N>::RS;
     __shared__ float2 lds[PlaneGeom<N>::WORDS];
     const int tid = threadIdx.x;
-    typename std::conditional<PACKED, PackedRegs<N, T>, TileRegs<N, N, T>>::type regs;
+    typename std::conditional<PACKED, PackedRegs<N, T>, TileRegs<N, N, T, stream_plane(N)>>::type regs;
     auto plane_base = [&](long i) {
         if constexpr (OUT) return i * N * N;
         const long b = i / nzp;
@@ -524,7 +539,7 @@ k_plane_pruned(const float2* in, float2* out, const float2* __restrict__ tw, lon
             const PlaneColOutBall<N> dst{out + plane_base(p), gz * gz, R2};
             run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
         } else {
-            const PlaneColOut<N> dst{out + plane_base(p)};
+            const PlaneColOut<N, false, stream_plane(N)> dst{out + plane_base(p)};
             run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
         }
         __syncthreads();

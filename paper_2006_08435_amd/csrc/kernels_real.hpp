@@ -99,7 +99,7 @@ k_plane_r2c(const float* in, float2* out, const float2* __restrict__ tw_x, const
     __shared__ float2 lds[G::WORDS];
     const int tid = threadIdx.x;
     const float2* in2 = reinterpret_cast<const float2*>(in);
-    TileRegs<N, M, T> regs;
+    TileRegs<N, M, T, stream_plane(N)> regs;
     long p = blockIdx.x;
     if (p < planes) regs.load(in2 + p * N * M, tid);
     for (; p < planes; p += gridDim.x) {
@@ -133,7 +133,7 @@ k_plane_c2r(const float2* in, float* out, const float2* __restrict__ tw_x, const
     __shared__ float2 lds[G::WORDS];
     const int tid = threadIdx.x;
     float2* out2 = reinterpret_cast<float2*>(out);
-    TileRegs<N, H, T> regs;
+    TileRegs<N, H, T, stream_plane(N)> regs;
     long p = blockIdx.x;
     if (p < planes) regs.load(in + p * N * H, tid);
     for (; p < planes; p += gridDim.x) {

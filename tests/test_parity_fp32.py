@@ -152,6 +152,23 @@ def test_full_batch_128(fft3d):
         assert np.all(np.abs(eF - n ** 3 * ef) <= 1e-5 * n ** 3 * ef)
 
 
+@pytest.mark.parametrize("n,batch", [(128, 2), (125, 3)])
+@pytest.mark.parametrize("direction", [-1, 1])
+def test_streaming_plane_pass(fft3d, n, batch, direction):
+    """At n = 125 and 128 a plane pass of 32 MB or more uses streaming loads
+    and stores, smaller ones the default policy.  Only the memory policy
+    differs: the first grid of the larger batch equals the same grid
+    transformed alone, and both meet the oracle."""
+    x = workloads.uniform_grid(n, 4200 + n + (direction > 0), batch=batch)
+    assert batch * n ** 3 * 8 >= 32 << 20 > n ** 3 * 8
+    big, _ = run(fft3d, x, direction)
+    one, _ = run(fft3d, x[:1], direction)
+    assert np.array_equal(big[0], one[0])
+    for j in (0, batch - 1):
+        ref = oracle.fft3d(x[j].astype(np.complex128), direction)
+        assert rel(big[j], ref) <= TOL, (j, rel(big[j], ref))
+
+
 def test_exec_argument_errors(fft3d):
     from paper_2006_08435_amd import _lib
     lib = _lib.lib()
