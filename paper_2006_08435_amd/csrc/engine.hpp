@@ -179,21 +179,25 @@ __device__ __forceinline__ void fft_stage(const Src& src, const Dst& dst, const 
 }
 
 // All stages of a length-N transform on an LDS tile, in place.
-// The tile is left in natural order; ends with a barrier.
+// The tile is left in natural order; ends with a barrier.  Every stage but
+// the last needs a barrier between its reads and its writes; in the last
+// stage each thread writes exactly the positions it read (j + q N/R), so it
+// needs none.
 template <int N, int S, int L, int T, int LS, int ES>
 __device__ __forceinline__ void fft_lds_all(float2* lds, const float2* __restrict__ tw, int tid,
                                             int valid_lines = L)
 {
     using P = Plan1D<N>;
+    constexpr int K = P::stages;
     const LdsAcc<LS, ES> a{lds};
-    if constexpr (P::stages > 0) { fft_stage<N, 0, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (P::stages > 1) { fft_stage<N, 1, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (P::stages > 2) { fft_stage<N, 2, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (P::stages > 3) { fft_stage<N, 3, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (P::stages > 4) { fft_stage<N, 4, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (P::stages > 5) { fft_stage<N, 5, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (P::stages > 6) { fft_stage<N, 6, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (P::stages > 7) { fft_stage<N, 7, S, L, T, true, true>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 0) { fft_stage<N, 0, S, L, T, true, (K > 1)>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 1) { fft_stage<N, 1, S, L, T, true, (K > 2)>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 2) { fft_stage<N, 2, S, L, T, true, (K > 3)>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 3) { fft_stage<N, 3, S, L, T, true, (K > 4)>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 4) { fft_stage<N, 4, S, L, T, true, (K > 5)>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 5) { fft_stage<N, 5, S, L, T, true, (K > 6)>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 6) { fft_stage<N, 6, S, L, T, true, (K > 7)>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 7) { fft_stage<N, 7, S, L, T, true, false>(a, a, tw, tid, valid_lines); __syncthreads(); }
 }
 
 }  // namespace fft3d

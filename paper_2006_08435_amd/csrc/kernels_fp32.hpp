@@ -56,8 +56,9 @@ struct LdsAcc2 {
 
 // Run stages [ST, stages) of the length-N schedule from LDS accessor `a` in
 // place, the last stage writing to `last` instead.  LAST_SYNC: `last`
-// aliases `a`, so the last stage also needs a barrier between its reads and
-// its writes.
+// aliases `a` with another layout, so the last stage also needs a barrier
+// between its reads and its writes.  With last == a it needs none: the last
+// stage of a Stockham schedule writes exactly the positions it read.
 template <int N, int S, int L, int T, int ST, bool LAST_SYNC, class A, class D>
 __device__ __forceinline__ void run_tail(const A& a, const D& last, const float2* __restrict__ tw, int tid,
                                          int valid = L)
@@ -290,13 +291,13 @@ k_cube(const float2* in, float2* out, const float2* __restrict__ tw)
     // y: lines (z, x), element stride YS
     {
         const LdsAcc2<N, G::ZS, 1, G::YS> a{lds};
-        run_tail<N, S, N * N, T, 0, true>(a, a, tw, tid);
+        run_tail<N, S, N * N, T, 0, false>(a, a, tw, tid);
         __syncthreads();
     }
     // z: lines (y, x), element stride ZS
     {
         const LdsAcc2<N, G::YS, 1, G::ZS> a{lds};
-        run_tail<N, S, N * N, T, 0, true>(a, a, tw, tid);
+        run_tail<N, S, N * N, T, 0, false>(a, a, tw, tid);
         __syncthreads();
     }
     lds_to_tile<N * N, N, G::YS, T>(lds, out + base, tid);
@@ -1054,7 +1055,7 @@ k_axis_hloc(float2* buf, const float2* __restrict__ tw_inv, const float2* __rest
     fft_stage<N, 0, 1, L, T, true, false>(src, a, tw_inv, tid, valid);
     __syncthreads();
     if constexpr (P::stages > 1) {
-        run_tail<N, 1, L, T, 1, true>(a, a, tw_inv, tid, valid);
+        run_tail<N, 1, L, T, 1, false>(a, a, tw_inv, tid, valid);
         __syncthreads();
     }
     // psi -> energy partial, s V psi
@@ -1154,7 +1155,7 @@ k_axis_density(const float2* buf, const float2* __restrict__ tw, AxisMap m, int 
         __syncthreads();
         if (b + 1 < batch) load0(b + 1);
         if constexpr (P::stages > 1) {
-            run_tail<N, 1, L, T, 1, true>(a, a, tw, tid, valid);
+            run_tail<N, 1, L, T, 1, false>(a, a, tw, tid, valid);
             __syncthreads();
         }
         const float f = occ[b];
