@@ -144,6 +144,17 @@ def main(argv=None):
     ms_step = e0.elapsed_time(e1) / args.steps
     print("[bench] %d steps, %.4f ms/step" % (args.steps, ms_step), file=sys.stderr, flush=True)
 
+    # The same steps timed one by one; where the working set would stay in
+    # the 256 MB Infinity Cache, also cold: a 512 MiB streaming copy (untimed)
+    # evicts it before each step.
+    timing = {"warm": step_distribution(step, args.steps, stream), "cold": None}
+    if a.numel() * 8 <= 64 << 20:
+        f0 = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        f1 = torch.empty_like(f0)
+        timing["cold"] = step_distribution(step, args.steps, stream,
+                                           flush=lambda: fft3d.stream_copy(f0, f1, stream))
+        del f0, f1
+
     # Per-kernel average launch durations (HIP events on the launch stream).
     passes = []
     for name, plan, src, dst in (("inverse", inv, a, b), ("forward", fwd, b, c)):
@@ -220,11 +231,12 @@ def main(argv=None):
                            "grids": sample},
         "kernels": [{"transform": p["transform"], "pass": p["pass"], "ms": round(p["ms"], 5)} for p in passes],
         "plans": {"inverse": inv.describe(), "forward": fwd.describe()},
+        "timing": timing,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "source_hash": source_hash(),
     }
-    print(json.dumps(out))
+    print(json.dumps(with_copy_peak(out)))
     return 0
 
 
@@ -246,6 +258,52 @@ def _time(fn, steps, warmup, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def copy_peak_gbs(nbytes, reps=20):
+    """Practical HBM ceiling: GB/s (read + write) of the library's streaming
+    copy (fft3d_stream_copy) of an nbytes buffer into another."""
+    import torch
+    import paper_2006_08435_amd as fft3d
+    n = max(16, nbytes // 16 * 16)
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    ms = _time(lambda: fft3d.stream_copy(src, dst, stream), reps, 3, stream)
+    del src, dst
+    return 2 * n / (ms * 1e-3) / 1e9
+
+
+def with_copy_peak(rec):
+    """Add to an HBM roofline the measured copy ceiling for the same bytes as
+    one launch of its kernel (half of them read, half written), and the
+    kernel's fraction of it."""
+    r = rec.get("roofline") or {}
+    ms = r.get("ms_per_launch") or r.get("ms_per_exec")
+    if r.get("bound") == "hbm" and ms:
+        gbs = copy_peak_gbs(int(r["achieved"] * 1e9 * ms * 1e-3 / 2))
+        r["copy_peak"] = round(gbs, 1)
+        r["frac_of_copy_peak"] = round(r["achieved"] / gbs, 4)
+    return rec
+
+
+def step_distribution(step, steps, stream, flush=None):
+    """Per-step device times (HIP events around each step only): mean,
+    median and min in ms.  flush, if given, runs untimed before each step."""
+    import torch
+    ev = []
+    for _ in range(steps):
+        if flush is not None:
+            flush()
+        e0, e1 = _events()
+        e0.record(stream)
+        step()
+        e1.record(stream)
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in ev)
+    return {"mean_ms": round(sum(ts) / len(ts), 5), "median_ms": round(ts[len(ts) // 2], 5),
+            "min_ms": round(ts[0], 5)}
 
 
 def _base_record(metric_value, unit, args, ms, desc, config, dtype="f32"):
@@ -332,7 +390,7 @@ def bench_mixed(args):
         "cpu_baseline": None if args.no_cpu_baseline else _cpu_oracle(xs[0], 64, 1, args.cpu_seconds, "64^3 grids"),
         "source_hash": source_hash(),
     })
-    print(json.dumps(rec))
+    print(json.dumps(with_copy_peak(rec)))
     return 0
 
 
@@ -434,7 +492,7 @@ def bench_energy(args):
         "cpu_baseline": None if args.no_cpu_baseline else _cpu_oracle(c, n, 1, args.cpu_seconds, "96^3 orbitals"),
         "source_hash": source_hash(),
     })
-    print(json.dumps(rec))
+    print(json.dumps(with_copy_peak(rec)))
     return 0
 
 
@@ -559,7 +617,7 @@ def bench_pruned(args):
         "cpu_baseline": None if args.no_cpu_baseline else _cpu_oracle(x, n, 1, args.cpu_seconds, "128^3 grids"),
         "source_hash": source_hash(),
     })
-    print(json.dumps(rec))
+    print(json.dumps(with_copy_peak(rec)))
     return 0
 
 
@@ -637,7 +695,7 @@ def bench_real(args):
         "cpu_baseline": None,
         "source_hash": source_hash(),
     })
-    print(json.dumps(rec))
+    print(json.dumps(with_copy_peak(rec)))
     return 0
 
 
@@ -726,7 +784,7 @@ def bench_q16(args, prec):
         "cpu_baseline": None,
         "source_hash": source_hash(),
     })
-    print(json.dumps(rec))
+    print(json.dumps(with_copy_peak(rec)))
     return 0
 
 

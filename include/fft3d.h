@@ -259,6 +259,17 @@ int fft3d_dequantize(int precision, long rows, int row_len, const void *in_scale
                      fft3d_stream_t stream);
 
 /*
+ * Measurement aid, not part of the transform: copies `bytes` bytes from src
+ * to dst (device pointers, 16-byte aligned, not overlapping; bytes a
+ * multiple of 16) on `stream` with 16-byte non-temporal loads and stores in
+ * one sweep.  Timing it on buffers the size of a transform's input gives the
+ * practical HBM bandwidth (read + write) that the transform passes are
+ * compared with, beside the nominal 8 TB/s.  bytes == 0 is a no-op.
+ * Returns FFT3D_OK, FFT3D_E_INVALID_ARG, FFT3D_E_ALIGNMENT or FFT3D_E_LAUNCH.
+ */
+int fft3d_stream_copy(const void *src, void *dst, size_t bytes, fft3d_stream_t stream);
+
+/*
  * Heterogeneous batches in one launch.  `count` groups (1 <= count <= 16);
  * group g holds batch[g] cubic grids of nx[g] = ny[g] = nz[g] points per
  * side (sizes 24, 30, 32, 36, 40, 48, 50, 60, 64, 72, 80, 90, 96, 100, 120,

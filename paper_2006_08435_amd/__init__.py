@@ -396,5 +396,17 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-__all__ = ["Plan", "PlanMany", "RealPlan", "rfftn", "irfftn", "get_plan", "quantize", "dequantize", "scaled16_bytes", "fftn", "ifftn", "Fft3dError", "FFT3D_FORWARD",
+def stream_copy(src, dst, stream=None):
+    """Copy device tensor src into dst (same byte size, contiguous) with the
+    library's streaming copy kernel: the measured HBM ceiling the transform
+    passes are compared with."""
+    nbytes = src.numel() * src.element_size()
+    if not (src.is_contiguous() and dst.is_contiguous()) or dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("stream_copy takes two contiguous tensors of the same byte size")
+    _lib.check(_lib.lib().fft3d_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, _stream_handle(stream)),
+               "fft3d_stream_copy")
+    return dst
+
+
+__all__ = ["Plan", "PlanMany", "RealPlan", "rfftn", "irfftn", "get_plan", "quantize", "dequantize", "scaled16_bytes", "stream_copy", "fftn", "ifftn", "Fft3dError", "FFT3D_FORWARD",
            "FFT3D_INVERSE", "FFT3D_FP32", "FFT3D_FP16_SCALED", "FFT3D_BF16_SCALED"]

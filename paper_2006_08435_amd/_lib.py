@@ -52,6 +52,7 @@ SIGNATURES = {
     "fft3d_exec_packed": (_ci, [_vp, _vp, _vp, _vp]),
     "fft3d_quantize": (_ci, [_ci, ctypes.c_long, _ci, _vp, _vp, _vp]),
     "fft3d_dequantize": (_ci, [_ci, ctypes.c_long, _ci, _vp, _vp, _vp]),
+    "fft3d_stream_copy": (_ci, [_vp, _vp, ctypes.c_size_t, _vp]),
     "fft3d_plan_many": (_vp, [_ci, _vp, _vp, _vp, _vp, _ci, _ci]),
     "fft3d_exec_many": (_ci, [_vp, _vp, _vp, _vp]),
     "fft3d_plan_set_schedule": (_ci, [_vp, _ci, _ci]),

@@ -661,6 +661,17 @@ int fft3d_dequantize(int precision, long rows, int row_len, const void* in, void
     return FFT3D_OK;
 }
 
+int fft3d_stream_copy(const void* src, void* dst, size_t bytes, fft3d_stream_t stream)
+{
+    if ((bytes && (!src || !dst)) || bytes % 16) return FFT3D_E_INVALID_ARG;
+    if (((uintptr_t)src % 16) || ((uintptr_t)dst % 16)) return FFT3D_E_ALIGNMENT;
+    if (launch_stream_copy(src, dst, (long)(bytes / 16), reinterpret_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
 static unsigned* timeouts_ptr(fft3d_plan_t p)
 {
     if (!p->many && p->fused_xcd) return &reinterpret_cast<XcdCtl*>(p->ctl)->timeouts;

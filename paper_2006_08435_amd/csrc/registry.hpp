@@ -99,6 +99,9 @@ hipError_t launch_quantize(int fmt, const float2* in, long rows, int C, unsigned
 hipError_t launch_dequantize(int fmt, const unsigned* pay, const signed char* ex, long rows, int C, float2* out,
                              hipStream_t st);
 
+// Streaming copy of n16 16-byte elements (k_copy.hip).
+hipError_t launch_stream_copy(const void* src, void* dst, long n16, hipStream_t st);
+
 // Kernel geometry (threads, LDS bytes) for diagnostics.
 struct KernelInfo {
     int threads;

@@ -80,6 +80,16 @@ def test_null_handles():
     assert lib.fft3d_density(None, None, None, None, None, None) == -1
 
 
+def test_stream_copy_argument_checks():
+    """The measurement copy checks its arguments before any HIP call."""
+    lib = _lib().lib()
+    assert lib.fft3d_stream_copy(None, None, 16, None) == -1
+    assert lib.fft3d_stream_copy(4096, 8192, 15, None) == -1
+    assert lib.fft3d_stream_copy(4104, 8192, 16, None) == -6
+    assert lib.fft3d_stream_copy(4096, 8200, 16, None) == -6
+    assert lib.fft3d_stream_copy(None, None, 0, None) == 0
+
+
 def test_strerror_covers_codes():
     lib = _lib().lib()
     seen = set()
