@@ -330,6 +330,19 @@ int fft3d_energy_fwd(fft3d_plan_t plan, const void *c, const float *V, void *psi
                      fft3d_stream_t stream);
 
 /*
+ * E alone, for schedules that recompute psi in the backward pass
+ * (fft3d_energy_bwd with have_psi == 0): the same E as fft3d_energy_fwd (the
+ * same FP32 products summed in the same FP64 order, so bit-identical), with
+ * psi summed on chip and never written.  `work` (device, the size of c)
+ * receives the xy-transformed intermediate; its contents afterwards are
+ * unspecified.  work == c is allowed and then overwrites c.  One read of c,
+ * one write and one read of the intermediate: 3 sweeps instead of 4.
+ * Plans and return codes as for fft3d_energy_fwd.
+ */
+int fft3d_energy(fft3d_plan_t plan, const void *c, const float *V, void *work, double *E_dev,
+                 fft3d_stream_t stream);
+
+/*
  * The local-potential operator itself, out_n = s * forward(V * inverse(c_n))
  * (both unnormalised; s = scale_dev[0] if scale_dev is not NULL, else 1):
  * the product of Section I's operator evaluation, and half the energy

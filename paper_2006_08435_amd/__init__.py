@@ -390,7 +390,7 @@ def ifftn(x, out=None):
 
 def __getattr__(name):
     # autograd wrappers are imported lazily (they need torch at import time)
-    if name in ("FFT3D", "IFFT3D", "LocalPotentialEnergy", "local_potential_energy", "energy_and_psi"):
+    if name in ("FFT3D", "IFFT3D", "LocalPotentialEnergy", "local_potential_energy", "energy", "energy_and_psi"):
         from . import autograd
         return getattr(autograd, name)
     raise AttributeError(name)

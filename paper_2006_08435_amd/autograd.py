@@ -8,7 +8,8 @@
   psi_n = IFFT3D(c_n), computed by fft3d_energy_fwd (inverse transform with
   the sum fused into its last pass); backward = fft3d_energy_bwd, i.e.
   grad_c = FFT3D(2 gE V psi), with the 2 gE V factor fused into the first
-  pass.  Gradients follow PyTorch's convention for real functions of complex
+  pass.  With save_psi=False the forward is fft3d_energy (E only, psi never
+  written) and the backward recomputes psi inside the fused operator.  Gradients follow PyTorch's convention for real functions of complex
   tensors: dE/dRe(c) + i dE/dIm(c).
 """
 from __future__ import annotations
@@ -56,11 +57,15 @@ class LocalPotentialEnergy(torch.autograd.Function):
         cb, Vc = _check_energy_args(c, V)
         b, nz, ny, nx = cb.shape
         plan = get_plan(nx, ny, nz, b, "fp32", FFT3D_INVERSE)
-        psi = torch.empty_like(cb)
+        psi = torch.empty_like(cb)   # psi, or the intermediate of the E-only pass
         E = torch.empty((), dtype=torch.float64, device=cb.device)
         sh = int(torch.cuda.current_stream().cuda_stream)
-        _lib.check(_lib.lib().fft3d_energy_fwd(plan.handle, cb.data_ptr(), Vc.data_ptr(), psi.data_ptr(),
-                                               E.data_ptr(), sh), "fft3d_energy_fwd")
+        if save_psi:
+            _lib.check(_lib.lib().fft3d_energy_fwd(plan.handle, cb.data_ptr(), Vc.data_ptr(), psi.data_ptr(),
+                                                   E.data_ptr(), sh), "fft3d_energy_fwd")
+        else:   # psi is recomputed by the backward: E alone, psi never written
+            _lib.check(_lib.lib().fft3d_energy(plan.handle, cb.data_ptr(), Vc.data_ptr(), psi.data_ptr(),
+                                               E.data_ptr(), sh), "fft3d_energy")
         ctx.save_for_backward(psi if save_psi else cb, Vc)
         ctx.have_psi = bool(save_psi)
         ctx.squeeze = c.dim() == 3
@@ -83,6 +88,19 @@ class LocalPotentialEnergy(torch.autograd.Function):
 def local_potential_energy(c, V, save_psi: bool = True):
     """E = sum_n sum_r V(r) |IFFT3D(c_n)(r)|^2 (differentiable in c)."""
     return LocalPotentialEnergy.apply(c, V, save_psi)
+
+
+def energy(c, V):
+    """E alone (fft3d_energy: psi is summed on chip and never written)."""
+    cb, Vc = _check_energy_args(c, V)
+    b, nz, ny, nx = cb.shape
+    plan = get_plan(nx, ny, nz, b, "fp32", FFT3D_INVERSE)
+    work = torch.empty_like(cb)
+    E = torch.empty((), dtype=torch.float64, device=cb.device)
+    sh = int(torch.cuda.current_stream().cuda_stream)
+    _lib.check(_lib.lib().fft3d_energy(plan.handle, cb.data_ptr(), Vc.data_ptr(), work.data_ptr(), E.data_ptr(), sh),
+               "fft3d_energy")
+    return E
 
 
 def energy_and_psi(c, V):

@@ -478,8 +478,10 @@ int fft3d_exec_pass(fft3d_plan_t p, int pass, const void* in, void* out, fft3d_s
 
 // Two-pass transform of sign `sign` (plane pass, then z pass) with the
 // optional gradient prologue (V, gE) and energy epilogue (V, E partials).
+// epilogue: 0 none, 1 E summed while psi is stored, 2 E only (dst then
+// holds the xy-transformed intermediate).
 static hipError_t energy_transform(const fft3d_plan_s* p, int sign, const float2* src, float2* dst,
-                                   const float* V, const double* gE, bool epilogue, hipStream_t st)
+                                   const float* V, const double* gE, int epilogue, hipStream_t st)
 {
     const int n = p->nx, nz = p->nz;
     const bool same = sign == p->direction;
@@ -509,7 +511,22 @@ int fft3d_energy_fwd(fft3d_plan_t p, const void* c, const float* V, void* psi, d
     if (rc != FFT3D_OK) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = energy_transform(p, FFT3D_INVERSE, static_cast<const float2*>(c), static_cast<float2*>(psi), V,
-                                    nullptr, true, st);
+                                    nullptr, 1, st);
+    if (e == hipSuccess) e = launch_sum_partials(p->partials, p->n_partials, E_dev, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT3D_E_LAUNCH;
+    }
+    return FFT3D_OK;
+}
+
+int fft3d_energy(fft3d_plan_t p, const void* c, const float* V, void* work, double* E_dev, fft3d_stream_t stream)
+{
+    const int rc = energy_args(p, c, work, V, E_dev);
+    if (rc != FFT3D_OK) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = energy_transform(p, FFT3D_INVERSE, static_cast<const float2*>(c), static_cast<float2*>(work), V,
+                                    nullptr, 2, st);
     if (e == hipSuccess) e = launch_sum_partials(p->partials, p->n_partials, E_dev, st);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -623,7 +640,7 @@ int fft3d_energy_bwd(fft3d_plan_t p, const void* c_or_psi, int have_psi, const f
     if (!have_psi)   // from c: the fused operator, 2 gE forward(V inverse(c)), psi never stored
         e = hloc_run(p, src, g, V, nullptr, gE_dev, 2.0f, false, st);
     else
-        e = energy_transform(p, FFT3D_FORWARD, src, g, V, gE_dev, false, st);
+        e = energy_transform(p, FFT3D_FORWARD, src, g, V, gE_dev, 0, st);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return FFT3D_E_LAUNCH;

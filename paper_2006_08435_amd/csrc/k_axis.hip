@@ -33,6 +33,11 @@ static hipError_t launch_axis_str(const float2* in, float2* out, const float2* t
                                   const float* V, double* partials, long vol, hipStream_t st)
 {
     const long blocks = axis_str_blocks(m.lines);
+    if (energy == 2) {
+        hipLaunchKernelGGL((k_axis_energy<N, S, kAxisLines>), dim3((unsigned)blocks),
+                           dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, tw, m, V, partials, vol);
+        return hipGetLastError();
+    }
     if (energy)
         hipLaunchKernelGGL((k_axis_str<N, S, kAxisLines, true>), dim3((unsigned)blocks),
                            dim3(AxisGeom<N, kAxisLines>::T), 0, st, in, out, tw, m, V, partials, vol, 0.0);

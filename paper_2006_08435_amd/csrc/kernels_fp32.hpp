@@ -830,7 +830,9 @@ struct AxisGeom {
 
 // Final-store accessor of the energy epilogue: stores psi and accumulates
 // V[r] |psi(r)|^2 (FP32 product, FP64 running sum) for this thread's points.
-struct EnergyStore {
+// STORE = false: the sum only, psi is not written.
+template <bool STORE>
+struct EnergyStoreT {
     const float2* src;
     float2* dst;
     long es;
@@ -839,10 +841,11 @@ struct EnergyStore {
     __device__ __forceinline__ float2 load(int, int e) const { return src[(long)e * es]; }
     __device__ __forceinline__ void store(int, int e, float2 val) const
     {
-        dst[(long)e * es] = val;
+        if constexpr (STORE) dst[(long)e * es] = val;
         acc += (double)(v[(long)e * es] * fmaf(val.x, val.x, val.y * val.y));
     }
 };
+using EnergyStore = EnergyStoreT<true>;
 
 // Fixed-order workgroup sum of one double per thread; result valid in thread 0.
 template <int T>
@@ -1003,6 +1006,45 @@ k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap
     }
 }
 
+
+// The energy pass without its output: the last pass of psi = IFFT(c), its
+// values only summed into sum V |psi|^2 (one FP64 partial per workgroup,
+// partials[blockIdx.x], the same products in the same order as the ENERGY
+// form of k_axis_str) and never written.
+template <int N, int S, int L>
+__global__ void __launch_bounds__((AxisGeom<N, L>::T))
+k_axis_energy(const float2* in, const float2* __restrict__ tw, AxisMap m, const float* __restrict__ V,
+              double* __restrict__ partials, long vol)
+{
+    using G = AxisGeom<N, L>;
+    using P = Plan1D<N>;
+    constexpr int T = G::T;
+    static_assert(T % L == 0, "each thread keeps one line");
+    __shared__ float2 lds[P::stages > 1 ? G::WORDS : 1];
+    __shared__ double red[T / 64];
+    const int tid = threadIdx.x;
+    const long l0 = (long)blockIdx.x * L;
+    const long li = l0 + tid % L;
+    const int valid = (int)((m.lines - l0) < L ? (m.lines - l0) : L);
+    long gbase = 0;
+    if (li < m.lines) {
+        const long o = li / m.nx;
+        const long x = li - o * m.nx;
+        gbase = (o / m.odiv) * m.shi + (o % m.odiv) * m.slo + x;
+    }
+    const GlobStrided g{in + gbase, nullptr, m.es};
+    const EnergyStoreT<false> eg{in + gbase, nullptr, m.es, V + (gbase % vol), 0.0};
+    if constexpr (P::stages == 1) {
+        fft_stage<N, 0, S, L, T, true, false>(g, eg, tw, tid, valid);
+    } else {
+        const LdsAcc<1, G::LP> a{lds};
+        fft_stage<N, 0, S, L, T, true, false>(g, a, tw, tid, valid);
+        __syncthreads();
+        run_tail<N, S, L, T, 1, false>(a, eg, tw, tid, valid);
+    }
+    const double t = block_sum<T>(eg.acc, red, tid);
+    if (tid == 0) partials[blockIdx.x] = t;
+}
 
 // --------------------------------------------------------------- x rows --
 

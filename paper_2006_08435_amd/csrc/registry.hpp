@@ -17,7 +17,8 @@ using PlaneFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, 
 using PlanePfFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, int grid, int scale,
                                  const float* V, const double* gE, int nz, hipStream_t st);
 // energy != 0: fused epilogue, V[r]|out(r)|^2 summed into one FP64 partial
-// per workgroup (axis_str_blocks(m) of them) at `partials`.
+// per workgroup (axis_str_blocks(m) of them) at `partials`; energy == 2: the
+// sum only, `out` is not written.
 using AxisStrFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, const AxisMap& m, int energy,
                                  const float* V, double* partials, long vol, hipStream_t st);
 using AxisRowFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long rows, hipStream_t st);

@@ -78,6 +78,7 @@ def test_null_handles():
     assert lib.fft3d_real_bytes(None) == 0
     assert lib.fft3d_apply_potential(None, None, None, None, None, None, None) == -1
     assert lib.fft3d_density(None, None, None, None, None, None) == -1
+    assert lib.fft3d_energy(None, None, None, None, None, None) == -1
 
 
 def test_stream_copy_argument_checks():

@@ -53,6 +53,43 @@ def test_energy_and_gradient_match_oracle(F, shape, b):
     assert E2.item() == E.item()            # same fused reduction, fixed order
 
 
+@pytest.mark.parametrize("shape,b", [((16, 16, 16), 3), ((24, 24, 20), 2), ((96, 96, 96), 2), ((30, 30, 30), 4),
+                                     ((8, 8, 1), 2), ((128, 128, 16), 1)])
+def test_energy_only_equals_fused_forward(F, shape, b):
+    """fft3d_energy sums the same FP32 products in the same FP64 order as
+    fft3d_energy_fwd (bit-identical E) and leaves c intact; with work == c it
+    overwrites c and gives the same E."""
+    c, V = make(shape, b, 7300 + sum(shape))
+    ct = torch.from_numpy(c).cuda()
+    Vt = torch.from_numpy(V).cuda()
+    E_fwd, _ = F.energy_and_psi(ct, Vt)
+    E_only = F.energy(ct, Vt)
+    torch.cuda.synchronize()
+    assert E_only.item() == E_fwd.item()
+    assert torch.equal(ct.cpu(), torch.from_numpy(c))
+    E_ref, _, _ = oracle.energy(c.astype(np.complex128), V.astype(np.float64), want_grad=False)
+    assert abs(E_only.item() - E_ref) <= E_TOL * abs(E_ref)
+    lib = F._lib.lib()
+    E2 = torch.zeros((), dtype=torch.float64, device="cuda")
+    plan = F.get_plan(shape[0], shape[1], shape[2], b, "fp32", F.FFT3D_INVERSE)
+    sh = int(torch.cuda.current_stream().cuda_stream)
+    assert lib.fft3d_energy(plan.handle, ct.data_ptr(), Vt.data_ptr(), ct.data_ptr(), E2.data_ptr(), sh) == 0
+    torch.cuda.synchronize()
+    assert E2.item() == E_fwd.item()
+
+
+def test_energy_only_rejections(F):
+    lib = F._lib.lib()
+    c = torch.zeros((1, 16, 16, 16), dtype=torch.complex64, device="cuda")
+    V = torch.zeros((16, 16, 16), dtype=torch.float32, device="cuda")
+    E = torch.zeros((), dtype=torch.float64, device="cuda")
+    p = F.Plan(16, 16, 16, 1, "fp32", F.FFT3D_INVERSE)
+    assert lib.fft3d_energy(p.handle, c.data_ptr(), V.data_ptr(), None, E.data_ptr(), None) == -1
+    assert lib.fft3d_energy(p.handle, c.data_ptr() + 8, V.data_ptr(), c.data_ptr(), E.data_ptr(), None) == -6
+    q = F.Plan(16, 16, 16, 1, "fp16", F.FFT3D_INVERSE)
+    assert lib.fft3d_energy(q.handle, c.data_ptr(), V.data_ptr(), c.data_ptr(), E.data_ptr(), None) == -7
+
+
 def test_saved_psi_and_recompute_agree(F):
     c, V = make((48, 48, 48), 3, 123)
     Vt = torch.from_numpy(V).cuda()
