@@ -78,8 +78,8 @@ def make_input(n, batch, seed0):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="batch128", choices=sorted(WORKLOADS) + list(EXTRA_WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -213,10 +213,21 @@ def main(argv=None):
             oracle.fft3d(y, -1)
             done += 1
         dt = time.time() - t0
+        # the same on one core, over a quarter of the time
+        oracle.set_threads(1)
+        done1, t1 = 0, time.time()
+        while time.time() - t1 < args.cpu_seconds / 4:
+            y = oracle.fft3d(x[done1 % batch].astype(np.complex128), 1)
+            oracle.fft3d(y, -1)
+            done1 += 1
+        dt1 = time.time() - t1
+        oracle.set_threads(threads)
         cpu = {"value": round(2 * 5.0 * n ** 3 * math.log2(n ** 3) * done / dt / 1e9, 3), "unit": "GFLOP/s",
                "cores": threads, "kind": "oracle",
                "sample": "%d grid transforms (cycling over the %d grids), inverse then forward, FP64 "
-                         "recursive radix-5/3/2 FFT, %.1f s" % (done, batch, dt)}
+                         "recursive radix-5/3/2 FFT, %.1f s" % (done, batch, dt),
+               "one_core_value": round(2 * 5.0 * n ** 3 * math.log2(n ** 3) * done1 / dt1 / 1e9, 3),
+               "one_core_sample": "%d grid transforms on 1 thread, %.1f s" % (done1, dt1)}
 
     out = {
         "metric": "3D FFT GFLOP/s (5N^3log2N^3/t) + HBM GB/s vs plain FP32, at rel-L2 err vs FP64",
@@ -313,6 +324,16 @@ def _base_record(metric_value, unit, args, ms, desc, config, dtype="f32"):
             "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": dict({"workload": desc}, **config)}
 
 
+def _many_kernels(desc):
+    """Kernels a heterogeneous plan runs, from its description."""
+    if "mode=persistent" in desc:
+        return "k_many<1,%s>" % desc.split("threads=")[1].split()[0]
+    if "mode=hybrid" in desc:
+        return "hybrid: k_plane_pf + k_axis_str for %s, k_many<1,%s> for the other groups" % (
+            desc.split("grouped=")[1].split()[0], desc.split("threads=")[1].split()[0])
+    return "grouped: k_plane_pf + k_axis_str per group"
+
+
 def bench_mixed(args):
     """256 x 64^3 plus one each of 48^3, 72^3, 96^3, 100^3, 120^3 (inverse):
     one persistent launch (replayed from a captured graph) against per-grid
@@ -358,6 +379,10 @@ def bench_mixed(args):
     batched = [(fft3d.Plan(n, n, n, b, "fp32", fft3d.FFT3D_INVERSE), i.data_ptr(), o.data_ptr())
                for (n, b), i, o in zip(groups, ins, outs)]
     group_ms = _time(lambda: [p.exec_ptr(a, b, sh) for p, a, b in batched], args.steps, args.warmup, stream)
+    # the hybrid schedule fixed (big groups plain, the rest in one persistent launch)
+    hyb = fft3d.PlanMany(groups, fft3d.FFT3D_INVERSE)
+    hyb.set_schedule(-1024, 2)
+    hybrid_ms = _time(lambda: hyb.exec_ptrs(iptr, optr, sh), args.steps, args.warmup, stream)
     g.replay()
     torch.cuda.synchronize()
     got = [o.cpu().numpy() for o in outs]
@@ -379,13 +404,13 @@ def bench_mixed(args):
         "compare_ms": {"tuned_graph": round(graph_ms, 4), "tuned_eager": round(eager_ms, 4),
                        "persistent_default_eager": round(default_ms, 4),
                        "per_grid_plain_launches_261": round(grid_ms, 4),
-                       "per_group_batched_launches_6": round(group_ms, 4)},
-        "plans": {"many_tuned": plan.describe(), "many_default": persistent_desc},
+                       "per_group_batched_launches_6": round(group_ms, 4),
+                       "hybrid_1024x2_eager": round(hybrid_ms, 4)},
+        "plans": {"many_tuned": plan.describe(), "many_default": persistent_desc, "many_hybrid": hyb.describe()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("mixed", "k_many") if "threads=" in plan.describe() else None,
-                     "kernel": ("k_many<1,%s>" % plan.describe().split("threads=")[1].split()[0]
-                                if "threads=" in plan.describe() else "grouped: k_plane_pf + k_axis_str per group"),
+                     "traffic": measured_traffic("mixed", "k_many") if "mode=persistent" in plan.describe() else None,
+                     "kernel": _many_kernels(plan.describe()),
                      "ms_per_exec": round(graph_ms, 5)},
         "cpu_baseline": None if args.no_cpu_baseline else _cpu_oracle(xs[0], 64, 1, args.cpu_seconds, "64^3 grids"),
         "source_hash": source_hash(),

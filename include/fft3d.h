@@ -277,8 +277,9 @@ int fft3d_stream_copy(const void *src, void *dst, size_t bytes, fft3d_stream_t s
  * persistent kernel launch: workgroups claim work items (xy-planes, then
  * xz-slabs of each grid) from a queue, and a grid's z work waits on a
  * per-grid counter of its finished planes.  A plan can instead run in the
- * grouped mode (two plain launches per group, the dense kernels), which the
- * tuner picks when it measures faster (few, large groups).  `in` and `out` are HOST arrays of
+ * grouped mode (two plain launches per group, the dense kernels) or a hybrid
+ * of the two (see fft3d_plan_set_schedule), which the tuner picks when they
+ * measure faster (few, large groups).  `in` and `out` are HOST arrays of
  * `count` device pointers, group g's buffer holding batch[g] grids in the
  * layout of fft3d_exec (in[g] == out[g] allowed).  The launch is
  * graph-capturable; a plan must not run concurrently with itself or with
@@ -294,8 +295,12 @@ fft3d_plan_t fft3d_plan_many(int count, const int *nx, const int *ny, const int 
                              int precision, int direction);
 int fft3d_exec_many(fft3d_plan_t plan, const void *const *in, void *const *out, fft3d_stream_t stream);
 /* Force a schedule of a many-plan: threads 512 or 1024 (the persistent
- * kernel, chunk 1..64 items per claim), or threads 0 (grouped mode: each
- * group's plane pass and z pass as plain launches, chunk ignored). */
+ * kernel, chunk 1..64 items per claim), threads 0 (grouped mode: each
+ * group's plane pass and z pass as plain launches, chunk ignored), or
+ * threads -512 / -1024 (hybrid mode: a group whose batch*n planes fill every
+ * compute unit with the plane kernel runs as in grouped mode, all other
+ * groups share one persistent launch with 512 / 1024 threads).  The tuner
+ * times all of them. */
 int fft3d_plan_set_schedule(fft3d_plan_t plan, int threads, int chunk);
 /* Time every schedule candidate on scratch buffers (synchronous), keep the
  * fastest and record it in the tuning cache. */

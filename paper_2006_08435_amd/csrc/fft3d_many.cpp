@@ -31,8 +31,10 @@ int device_cus(int dev)
 }
 
 // Work list: for every grid its plane items, and its slab items at least
-// `lag` list positions after its last plane item.
-std::vector<unsigned> build_items(const std::vector<ManyGrid>& grids, int threads, long lag)
+// `lag` list positions after its last plane item.  Grids of the groups
+// marked in `skip` (if given) are left out.
+std::vector<unsigned> build_items(const std::vector<ManyGrid>& grids, int threads, long lag,
+                                  const bool* skip = nullptr)
 {
     std::vector<unsigned> out;
     std::deque<std::pair<long, int>> ready;   // (list length when the planes ended, grid)
@@ -47,6 +49,7 @@ std::vector<unsigned> build_items(const std::vector<ManyGrid>& grids, int thread
         }
     };
     for (int g = 0; g < (int)grids.size(); ++g) {
+        if (skip && skip[grids[g].group]) continue;
         const int n = grids[g].n, per = many_per_item(n, threads);
         for (int i = 0; i < n; i += per) {
             out.push_back(many_item((unsigned)g, 0u, (unsigned)i));
@@ -61,10 +64,11 @@ std::vector<unsigned> build_items(const std::vector<ManyGrid>& grids, int thread
     return out;
 }
 
-size_t plan_lds(const ManyPlan& mp, int threads)
+size_t plan_lds(const ManyPlan& mp, int threads, const bool* skip = nullptr)
 {
     size_t m = 0;
     for (int g = 0; g < mp.ngroups; ++g) {
+        if (skip && skip[g]) continue;
         const size_t b = many_lds_bytes(mp.n[g], threads);
         m = b > m ? b : m;
     }
@@ -72,44 +76,68 @@ size_t plan_lds(const ManyPlan& mp, int threads)
 }
 
 // Apply a (threads, chunk) schedule: occupancy, grid, work list.  threads
-// 0 selects the grouped mode (nothing to prepare).
+// 0 selects the grouped mode (nothing to prepare); threads < 0 the hybrid
+// mode with |threads| threads for the persistent part: a group whose plane
+// pass alone fills every compute unit (batch * n planes >= the plane
+// kernel's resident workgroups) runs its two plain passes, the others share
+// one persistent launch.
 int apply_schedule(fft3d_plan_s* p, int threads, int chunk)
 {
     ManyPlan& mp = p->mp;
     if (threads == 0) {
         mp.threads = 0;
         mp.chunk = 1;
+        mp.hybrid = false;
         return FFT3D_OK;
     }
-    const size_t lds = plan_lds(mp, threads);
-    const int per_cu = many_blocks_per_cu(threads, lds);
-    if (per_cu < 1) return FFT3D_E_UNSUPPORTED;
-    const int resident = per_cu * device_cus(p->device);
-    const long lag = (long)resident * chunk + resident;
-    std::vector<unsigned> items = build_items(mp.grids, threads, lag);
-    if ((long)items.size() > mp.items_cap) return FFT3D_E_INVALID_ARG;
-    if (hipMemcpy(mp.d_items, items.data(), items.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipGetLastError();
-        return FFT3D_E_LAUNCH;
+    const bool hybrid = threads < 0;
+    const int t = hybrid ? -threads : threads;
+    const int cus = device_cus(p->device);
+    bool big[kMaxGroups] = {};
+    if (hybrid)
+        for (int g = 0; g < mp.ngroups; ++g)
+            big[g] = (long)mp.batch[g] * mp.n[g] >= (long)plane_pf_blocks_per_cu(mp.n[g]) * cus;
+    const bool* skip = hybrid ? big : nullptr;
+    const size_t lds = plan_lds(mp, t, skip);
+    long nitems = 0;
+    int grid = 1;
+    if (lds > 0) {   // at least one group runs in the persistent launch
+        const int per_cu = many_blocks_per_cu(t, lds);
+        if (per_cu < 1) return FFT3D_E_UNSUPPORTED;
+        const int resident = per_cu * cus;
+        const long lag = (long)resident * chunk + resident;
+        std::vector<unsigned> items = build_items(mp.grids, t, lag, skip);
+        if ((long)items.size() > mp.items_cap) return FFT3D_E_INVALID_ARG;
+        if (hipMemcpy(mp.d_items, items.data(), items.size() * sizeof(unsigned), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return FFT3D_E_LAUNCH;
+        }
+        nitems = (long)items.size();
+        const long claims = (nitems + chunk - 1) / chunk;
+        grid = (int)(claims < resident ? claims : resident);
     }
-    mp.nitems = (long)items.size();
-    mp.threads = threads;
+    mp.nitems = nitems;
+    mp.threads = t;
     mp.chunk = chunk;
     mp.lds = lds;
-    const long claims = (mp.nitems + chunk - 1) / chunk;
-    mp.grid = (int)(claims < resident ? claims : resident);
+    mp.grid = grid;
+    mp.hybrid = hybrid;
+    for (int g = 0; g < kMaxGroups; ++g) mp.big[g] = big[g];
     return FFT3D_OK;
 }
 
 // Grouped mode: for each group its plane pass and its z pass, as a dense
 // plan of that group would launch them (the persistent kernel's alternative
-// when the groups are few and large).
-hipError_t launch_grouped(const fft3d_plan_s* p, const void* const* in, void* const* out, hipStream_t st)
+// when the groups are few and large).  only (if given): the groups to run.
+hipError_t launch_grouped(const fft3d_plan_s* p, const void* const* in, void* const* out, hipStream_t st,
+                          const bool* only = nullptr)
 {
     const ManyPlan& mp = p->mp;
     const int cus = device_cus(p->device);
     hipError_t e = hipSuccess;
     for (int g = 0; g < mp.ngroups && e == hipSuccess; ++g) {
+        if (only && !only[g]) continue;
         const int n = mp.n[g];
         const long planes = (long)mp.batch[g] * n, resident = (long)plane_pf_blocks_per_cu(n) * cus;
         const float2* tw = p->d_tw + mp.twoff_host[n];
@@ -191,7 +219,7 @@ bool cache_lookup(const std::string& key, int& threads, int& chunk)
     int t = 0, c = 0;
     double ms = 0;
     if (std::sscanf(it->second.c_str(), "{\"threads\": %d, \"chunk\": %d, \"ms\": %lf}", &t, &c, &ms) != 3) return false;
-    if ((t != 0 && t != 512 && t != 1024) || c < 1 || c > 64) return false;
+    if ((t != 0 && t != 512 && t != 1024 && t != -512 && t != -1024) || c < 1 || c > 64) return false;
     threads = t;
     chunk = c;
     return true;
@@ -237,8 +265,9 @@ int tune(fft3d_plan_s* p)
     if (rc == FFT3D_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = FFT3D_E_LAUNCH;
     double best = 1e30;
     int bt = mp.threads, bc = mp.chunk;
-    // candidates: the grouped mode, then the persistent kernel's (threads, chunk)
-    const int cand_t[] = {0, 1024, 512};
+    // candidates: the grouped mode, then the persistent kernel's and the
+    // hybrid mode's (threads, chunk)
+    const int cand_t[] = {0, 1024, 512, -1024, -512};
     const int cand_c[] = {1, 2, 4, 8};
     for (int t : cand_t)
         for (int c : cand_c) {
@@ -277,6 +306,9 @@ int tune(fft3d_plan_s* p)
 hipError_t run_many(const fft3d_plan_s* p, const void* const* in, void* const* out, hipStream_t st)
 {
     if (p->mp.threads == 0) return launch_grouped(p, in, out, st);
+    hipError_t e = hipSuccess;
+    if (p->mp.hybrid) e = launch_grouped(p, in, out, st, p->mp.big);
+    if (e != hipSuccess || p->mp.nitems == 0) return e;
     const ManyArgs a = make_args(p, in, out);
     return launch_many(a, p->direction, p->mp.threads, p->mp.grid, p->mp.lds, st);
 }
@@ -403,9 +435,12 @@ int fft3d_exec_many(fft3d_plan_t p, const void* const* in, void* const* out, fft
 
 int fft3d_plan_set_schedule(fft3d_plan_t p, int threads, int chunk)
 {
-    if (!p || !p->many || (threads != 0 && threads != 512 && threads != 1024) || chunk < 1 || chunk > 64)
+    if (!p || !p->many || (threads != 0 && threads != 512 && threads != 1024 && threads != -512 && threads != -1024) ||
+        chunk < 1 || chunk > 64)
         return FFT3D_E_INVALID_ARG;
-    return apply_schedule(p, threads, chunk);
+    const int rc = apply_schedule(p, threads, chunk);
+    if (rc == FFT3D_OK) p->mp.tuned = false;   // a forced schedule, not the tuner's
+    return rc;
 }
 
 int fft3d_plan_tune(fft3d_plan_t p)
@@ -426,6 +461,18 @@ int many_describe(fft3d_plan_t p, char* buf, size_t len)
     if (p->mp.threads == 0) {
         d << " mode=grouped" << (p->mp.tuned ? " tuned" : " default") << (p->direction < 0 ? " forward" : " inverse")
           << " kernels=k_plane_pf,k_axis_str per group";
+    } else if (p->mp.hybrid) {
+        d << " mode=hybrid grouped=";
+        bool first = true;
+        for (int g = 0; g < p->mp.ngroups; ++g)
+            if (p->mp.big[g]) {
+                d << (first ? "" : ",") << p->mp.n[g] << "^3x" << p->mp.batch[g];
+                first = false;
+            }
+        if (first) d << "none";
+        d << " threads=" << p->mp.threads << " chunk=" << p->mp.chunk << " workgroups=" << p->mp.grid
+          << " lds=" << p->mp.lds << " items=" << p->mp.nitems << (p->mp.tuned ? " tuned" : " default")
+          << (p->direction < 0 ? " forward" : " inverse") << " kernels=k_plane_pf,k_axis_str per big group + k_many";
     } else {
         d << " mode=persistent threads=" << p->mp.threads << " chunk=" << p->mp.chunk << " workgroups=" << p->mp.grid
           << " lds=" << p->mp.lds << " items=" << p->mp.nitems << (p->mp.tuned ? " tuned" : " default")

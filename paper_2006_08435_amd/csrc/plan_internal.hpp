@@ -45,6 +45,10 @@ struct ManyPlan {
     int* d_twoff = nullptr;
     int threads = 1024;   // 0: grouped mode (two plain passes per group) instead of the persistent kernel
     int chunk = 2;
+    // hybrid mode: the groups marked big (enough planes to fill the device)
+    // run their two plain passes, the others share one persistent launch
+    bool hybrid = false;
+    bool big[kMaxGroups] = {};
     int twoff_host[129] = {};   // offset of the length-n table in the plan's twiddles
     int grid = 1;
     size_t lds = 0;

@@ -93,6 +93,47 @@ def test_grouped_mode(F):
         assert rel(y, z) <= 1e-6
 
 
+def test_hybrid_mode(F):
+    """threads < 0: a group with enough planes to fill the device runs its
+    plain passes (bit-identical to grouped mode), the others share one
+    persistent launch (bit-identical to the persistent mode's results for
+    those grids)."""
+    groups = [(64, 64), (72, 1), (48, 2), (100, 1)]
+    xs = inputs(groups, 9)
+    plan = F.PlanMany(groups, 1)
+    plan.set_schedule(0, 1)
+    grouped = run(plan, xs)
+    plan.set_schedule(1024, 2)
+    pers = run(plan, xs)
+    plan.set_schedule(-1024, 2)
+    d = plan.describe()
+    assert "mode=hybrid grouped=64^3x64 " in d and "threads=1024 chunk=2" in d, d
+    got = run(plan, xs)
+    assert np.array_equal(got[0], grouped[0])
+    for a, b in zip(got[1:], pers[1:]):
+        assert np.array_equal(a, b)
+    for (n, b), x, y in zip(groups, xs, got):
+        for j in (0, b - 1):
+            assert rel(y[j], oracle.fft3d(x[j].astype(np.complex128), 1)) <= TOL, (n, j)
+    from paper_2006_08435_amd import _lib
+    assert _lib.lib().fft3d_plan_check(plan.handle) == 0
+
+
+@pytest.mark.parametrize("groups,mode", [([(48, 2), (36, 3)], "grouped=none"), ([(64, 64)], "items=0")])
+def test_hybrid_degenerate_splits(F, groups, mode):
+    """All groups small: the persistent launch alone; all big: plain passes
+    alone (no persistent launch)."""
+    xs = inputs(groups, 19)
+    plan = F.PlanMany(groups, -1)
+    plan.set_schedule(-512, 4)
+    assert mode in plan.describe(), plan.describe()
+    got = run(plan, xs)
+    plan.set_schedule(0 if mode == "items=0" else 512, 4)
+    want = run(plan, xs)
+    for a, b in zip(got, want):
+        assert np.array_equal(a, b)
+
+
 def test_matches_plain_per_grid_execs(F):
     groups = [(96, 2), (60, 3)]
     xs = inputs(groups, 21)
@@ -118,9 +159,10 @@ def test_inplace_and_repeat(F):
         assert np.array_equal(a, b.cpu().numpy())
 
 
-@pytest.mark.parametrize("threads,chunk", [(1024, 2), (0, 1)])
-def test_graph_capture_replays_match_eager(F, threads, chunk):
-    groups = [(64, 4), (80, 1), (36, 2)]
+@pytest.mark.parametrize("threads,chunk,groups", [(1024, 2, [(64, 4), (80, 1), (36, 2)]),
+                                                  (0, 1, [(64, 4), (80, 1), (36, 2)]),
+                                                  (-1024, 2, [(64, 48), (80, 1), (36, 2)])])
+def test_graph_capture_replays_match_eager(F, threads, chunk, groups):
     xs = inputs(groups, 41)
     plan = F.PlanMany(groups, -1)
     plan.set_schedule(threads, chunk)
@@ -154,20 +196,21 @@ def test_tuner_and_cache(F, tmp_path, monkeypatch):
     assert "tuned" in p1.describe()
     d = json.loads(cache.read_text())
     (key, val), = d.items()
-    assert val["threads"] in (0, 512, 1024) and 1 <= val["chunk"] <= 8 and val["ms"] > 0
+    assert val["threads"] in (0, 512, 1024, -512, -1024) and 1 <= val["chunk"] <= 8 and val["ms"] > 0
     monkeypatch.delenv("FFT3D_TUNE")
     p2 = F.PlanMany(groups, -1)            # read back from the cache
     assert "tuned" in p2.describe()
     if val["threads"] == 0:
         assert "mode=grouped" in p2.describe()
     else:
-        assert "threads=%d chunk=%d" % (val["threads"], val["chunk"]) in p2.describe()
+        assert "threads=%d chunk=%d" % (abs(val["threads"]), val["chunk"]) in p2.describe()
+        assert ("mode=hybrid" in p2.describe()) == (val["threads"] < 0)
     cache.write_text("{ this is not json")  # a corrupt cache falls back to the default
     p3 = F.PlanMany(groups, -1)
     assert "default" in p3.describe()
     xs = inputs(groups, 51)
     for a, b in zip(run(p1, xs), run(p3, xs)):
-        if val["threads"] == 0:             # other kernels: equal to rounding
+        if val["threads"] <= 0:             # other kernels (for some groups): equal to rounding
             assert rel(a, b) <= 1e-6
         else:
             assert np.array_equal(a, b)
