@@ -209,19 +209,22 @@ __device__ __forceinline__ void mfma_stage16(float2* lds, int tid)
 
 // All stages of a length-N KIND-1 transform on an LDS tile, in place; ends
 // with a barrier.  MFMA: radix-16 stage on the matrix cores (else the same
-// stage as an FP32 radix-16 butterfly on the vector ALUs).
+// stage as an FP32 radix-16 butterfly on the vector ALUs).  The last vector
+// stage writes exactly the positions each thread read, so it needs no
+// barrier between its reads and writes.
 template <int N, int S, int L, int T, int LS, int ES, bool MFMA>
 __device__ __forceinline__ void q16_fft_lds(float2* lds, const float2* __restrict__ tw, int tid)
 {
     using P = Plan1D<N, 1>;
+    constexpr int K = P::stages;
     const LdsAcc<LS, ES> a{lds};
     if constexpr (MFMA) mfma_stage16<N, S, L, T, LS, ES>(lds, tid);
-    else fft_stage_p<P, 0, S, L, T, true, true>(a, a, tw, tid);
+    else fft_stage_p<P, 0, S, L, T, true, (K > 1)>(a, a, tw, tid);
     __syncthreads();
-    if constexpr (P::stages > 1) { fft_stage_p<P, 1, S, L, T, true, true>(a, a, tw, tid); __syncthreads(); }
-    if constexpr (P::stages > 2) { fft_stage_p<P, 2, S, L, T, true, true>(a, a, tw, tid); __syncthreads(); }
-    if constexpr (P::stages > 3) { fft_stage_p<P, 3, S, L, T, true, true>(a, a, tw, tid); __syncthreads(); }
-    if constexpr (P::stages > 4) { fft_stage_p<P, 4, S, L, T, true, true>(a, a, tw, tid); __syncthreads(); }
+    if constexpr (K > 1) { fft_stage_p<P, 1, S, L, T, true, (K > 2)>(a, a, tw, tid); __syncthreads(); }
+    if constexpr (K > 2) { fft_stage_p<P, 2, S, L, T, true, (K > 3)>(a, a, tw, tid); __syncthreads(); }
+    if constexpr (K > 3) { fft_stage_p<P, 3, S, L, T, true, (K > 4)>(a, a, tw, tid); __syncthreads(); }
+    if constexpr (K > 4) { fft_stage_p<P, 4, S, L, T, true, false>(a, a, tw, tid); __syncthreads(); }
 }
 
 // Pass A: planes p = b * N + z, persistent over `planes` with the next plane
