@@ -212,19 +212,84 @@ __device__ __forceinline__ void mfma_stage16(float2* lds, int tid)
 // stage as an FP32 radix-16 butterfly on the vector ALUs).  The last vector
 // stage writes exactly the positions each thread read, so it needs no
 // barrier between its reads and writes.
-template <int N, int S, int L, int T, int LS, int ES, bool MFMA>
+// SKIP_LAST: stop before the last stage (q16_last_stage_store runs it).
+template <int N, int S, int L, int T, int LS, int ES, bool MFMA, bool SKIP_LAST = false>
 __device__ __forceinline__ void q16_fft_lds(float2* lds, const float2* __restrict__ tw, int tid)
 {
     using P = Plan1D<N, 1>;
-    constexpr int K = P::stages;
+    constexpr int K = SKIP_LAST ? P::stages - 1 : P::stages;
+    static_assert(K >= 1, "at least one stage runs here");
     const LdsAcc<LS, ES> a{lds};
+    // a stage needs the barrier between its reads and writes unless it is
+    // the schedule's true last stage
+    constexpr int KL = P::stages;
     if constexpr (MFMA) mfma_stage16<N, S, L, T, LS, ES>(lds, tid);
-    else fft_stage_p<P, 0, S, L, T, true, (K > 1)>(a, a, tw, tid);
+    else fft_stage_p<P, 0, S, L, T, true, (KL > 1)>(a, a, tw, tid);
     __syncthreads();
-    if constexpr (K > 1) { fft_stage_p<P, 1, S, L, T, true, (K > 2)>(a, a, tw, tid); __syncthreads(); }
-    if constexpr (K > 2) { fft_stage_p<P, 2, S, L, T, true, (K > 3)>(a, a, tw, tid); __syncthreads(); }
-    if constexpr (K > 3) { fft_stage_p<P, 3, S, L, T, true, (K > 4)>(a, a, tw, tid); __syncthreads(); }
+    if constexpr (K > 1) { fft_stage_p<P, 1, S, L, T, true, (KL > 2)>(a, a, tw, tid); __syncthreads(); }
+    if constexpr (K > 2) { fft_stage_p<P, 2, S, L, T, true, (KL > 3)>(a, a, tw, tid); __syncthreads(); }
+    if constexpr (K > 3) { fft_stage_p<P, 3, S, L, T, true, (KL > 4)>(a, a, tw, tid); __syncthreads(); }
     if constexpr (K > 4) { fft_stage_p<P, 4, S, L, T, true, false>(a, a, tw, tid); __syncthreads(); }
+}
+
+// Whether the last stage of a length-N KIND-1 transform over N lines can run
+// with one wave per butterfly index j: the stage has N / R butterflies per
+// line, so T / 64 == N / R waves each take all N lines (N / 64 per lane) of
+// one j, and every output row j + q N / R lies inside one wave.
+template <int N, int T>
+constexpr bool q16_wave_rows()
+{
+    using P = Plan1D<N, 1>;
+    return P::stages > 1 && N % 64 == 0 && T == 64 * (N / P::radix(P::stages - 1));
+}
+
+// Last stage of the transform along the tile's elements (lines = x, LDS
+// address x + e * ES) with one wave per butterfly index, requantized
+// straight from registers: output row r = element index, stored as scaled16
+// at pay[r * rstride + x] with its exponent at ex[r * estride].  The same
+// butterflies, twiddles, row maxima and roundings as running the stage in
+// LDS and then q16_store_rows, without writing the tile back to LDS and
+// reading it again (the compiler may contract a few multiply-adds
+// differently, so single values can differ in the last place).  Used by
+// the plane pass; in the slab pass the extra live registers spill.
+template <int N, int S, int T, int ES, int FMT>
+__device__ __forceinline__ void q16_last_stage_store(const float2* lds, const float2* __restrict__ tw,
+                                                     unsigned* pay, long rstride, signed char* ex, long estride,
+                                                     int tid)
+{
+    using P = Plan1D<N, 1>;
+    constexpr int ST = P::stages - 1, R = P::radix(ST), NS = P::ns(ST), M = N / R, IT = N / 64;
+    static_assert(q16_wave_rows<N, T>() && NS == M, "one wave per butterfly index of the last stage");
+    const int lane = tid & 63;
+    const int j = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const float2* __restrict__ w = tw + P::tw_off(ST) + (j % NS) * (R - 1);
+    float2 v[IT][R];
+    float m[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) m[q] = 0.f;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int x = lane + 64 * it;
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[it][q] = lds[x + (j + q * M) * ES];
+#pragma unroll
+        for (int q = 1; q < R; ++q) v[it][q] = cmul(v[it][q], w[q - 1]);
+        dft<R, S>(v[it]);
+#pragma unroll
+        for (int q = 0; q < R; ++q) m[q] = fmaxf(m[q], fmaxf(fabsf(v[it][q].x), fabsf(v[it][q].y)));
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m[q] = fmaxf(m[q], __shfl_xor(m[q], o, 64));
+        const int r = j + q * NS, e = row_exponent(m[q]);
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int x = lane + 64 * it;
+            pay[r * rstride + x] = enc16<FMT>(ldexpf(v[it][q].x, -e)) | (enc16<FMT>(ldexpf(v[it][q].y, -e)) << 16);
+        }
+        if (lane == 0) ex[r * estride] = (signed char)e;
+    }
 }
 
 // Pass A: planes p = b * N + z, persistent over `planes` with the next plane
@@ -251,8 +316,13 @@ k_q16_plane(const unsigned* in_pay, const signed char* in_exp, unsigned* mid_pay
         if (pn < planes) regs.load(in_pay + pn * N * N, N, in_exp + pn * N, 1, tid);
         __syncthreads();
         q16_fft_lds<N, S, N, T, RS, 1, MFMA>(lds, tw, tid);   // x: lines = rows
-        q16_fft_lds<N, S, N, T, 1, RS, MFMA>(lds, tw, tid);   // y: lines = columns
-        q16_store_rows<N, N, RS, T, kFmtF16>(lds, mid_pay + p * N * N, N, mid_exp + p * N, 1, tid);
+        if constexpr (q16_wave_rows<N, T>()) {                // y: lines = columns
+            q16_fft_lds<N, S, N, T, 1, RS, MFMA, true>(lds, tw, tid);
+            q16_last_stage_store<N, S, T, RS, kFmtF16>(lds, tw, mid_pay + p * N * N, N, mid_exp + p * N, 1, tid);
+        } else {
+            q16_fft_lds<N, S, N, T, 1, RS, MFMA>(lds, tw, tid);
+            q16_store_rows<N, N, RS, T, kFmtF16>(lds, mid_pay + p * N * N, N, mid_exp + p * N, 1, tid);
+        }
     }
 }
 
