@@ -87,7 +87,7 @@ def main(argv=None):
                     help="only run a plain device copy of one workload buffer (for counter scaling)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X; "
+        print("bench.py measures one GPU only: the library runs on a single MI355X; "
               "run with --gpus 1", file=sys.stderr)
         return 2
 

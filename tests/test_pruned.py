@@ -13,7 +13,7 @@ reach the sphere.  What they compute is still the DFT of Eq. (1).  Bars:
   literal zeros for loads of zeros and drops stores.  The compiler may
   contract a few multiply-adds of the pruned kernels into FMAs differently,
   so the bar is FP32 rounding: every element within 16 ulp of the largest
-  magnitude.  The inverse kernels are in fact bit-identical in this build and
+  magnitude.  The inverse kernels are in fact bit-identical as compiled and
   the tests say so (==);
 * the FP32 tolerance (relative L2 <= 5e-6) against the FP64 oracle.
 """
