@@ -192,9 +192,11 @@ def test_orbital_batch_128x96(F):
     V = workloads.smooth_potential(n, workloads.SEED_POTENTIAL)
     ct = torch.from_numpy(c).cuda().requires_grad_(True)
     Vt = torch.from_numpy(V).cuda()
-    E = F.local_potential_energy(ct, Vt, save_psi=False)
+    E = F.local_potential_energy(ct, Vt, save_psi=False)   # E alone, psi recomputed in backward
     E.backward()
+    E_psi, _ = F.energy_and_psi(ct.detach(), Vt)             # E with psi stored
     torch.cuda.synchronize()
+    assert E_psi.item() == E.item()
     E_ref, _, g_ref = oracle.energy(c.astype(np.complex128), V.astype(np.float64))
     assert abs(E.item() - E_ref) <= E_TOL * abs(E_ref), (E.item(), E_ref)
     assert rel(ct.grad.cpu().numpy(), g_ref) <= 5e-6
