@@ -77,16 +77,21 @@ struct Q16Regs {
     static_assert(NR <= T, "one exponent per thread");
     unsigned u[IT];
     int ev;
-    // rows r at pay + r * rstride, exponents at ex[r * estride]
+    // rows r at pay + r * rstride, exponents at ex[r * estride]; OFF32:
+    // 32-bit element offsets from pay (the tile spans < 2^32 elements)
+    template <bool OFF32 = false>
     __device__ __forceinline__ void load(const unsigned* pay, long rstride, const signed char* ex, long estride,
                                          int tid)
     {
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
             const int i = tid + k * T;
-            if (UNITS % T == 0 || i < UNITS) u[k] = pay[(i / N) * rstride + (i % N)];
+            if (UNITS % T == 0 || i < UNITS) {
+                if constexpr (OFF32) u[k] = pay[(unsigned)((i / N) * rstride + (i % N))];
+                else u[k] = pay[(i / N) * rstride + (i % N)];
+            }
         }
-        if (tid < NR) ev = ex[tid * estride];
+        if (tid < NR) ev = OFF32 ? ex[(unsigned)(tid * estride)] : ex[tid * estride];
     }
     // exact FP32 values into the LDS tile (row stride RS); lds_e must hold
     // the exponents (see put_exponent) and be visible to every thread
@@ -251,10 +256,11 @@ constexpr bool q16_wave_rows()
 // LDS and then q16_store_rows, without writing the tile back to LDS and
 // reading it again (the compiler may contract a few multiply-adds
 // differently, so single values can differ in the last place).  Used by
-// the plane pass; in the slab pass the extra live registers spill.
+// both passes; the slab pass loads its tile with 32-bit offsets
+// (Q16Regs::load<true>), which frees the registers this stage needs.
 template <int N, int S, int T, int ES, int FMT>
 __device__ __forceinline__ void q16_last_stage_store(const float2* lds, const float2* __restrict__ tw,
-                                                     unsigned* pay, long rstride, signed char* ex, long estride,
+                                                     unsigned* pay, int rstride, signed char* ex, int estride,
                                                      int tid)
 {
     using P = Plan1D<N, 1>;
@@ -286,9 +292,10 @@ __device__ __forceinline__ void q16_last_stage_store(const float2* lds, const fl
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             const int x = lane + 64 * it;
-            pay[r * rstride + x] = enc16<FMT>(ldexpf(v[it][q].x, -e)) | (enc16<FMT>(ldexpf(v[it][q].y, -e)) << 16);
+            pay[(unsigned)(r * rstride + x)] =
+                enc16<FMT>(ldexpf(v[it][q].x, -e)) | (enc16<FMT>(ldexpf(v[it][q].y, -e)) << 16);
         }
-        if (lane == 0) ex[r * estride] = (signed char)e;
+        if (lane == 0) ex[(unsigned)(r * estride)] = (signed char)e;
     }
 }
 
@@ -342,16 +349,24 @@ k_q16_slab(const unsigned* mid_pay, const signed char* mid_exp, unsigned* out_pa
     // row index of (b, z = 0, y); rows of successive z are N apart
     auto row0 = [](long s) { return (s / N) * N * N + (s % N); };
     long s = blockIdx.x;
-    if (s < slabs) regs.load(mid_pay + row0(s) * N, (long)N * N, mid_exp + row0(s), N, tid);
+    if (s < slabs) regs.template load<true>(mid_pay + row0(s) * N, (long)N * N, mid_exp + row0(s), N, tid);
     for (; s < slabs; s += gridDim.x) {
         regs.put_exponent(lds_e, tid);
         __syncthreads();
         regs.template to_lds<RS, kFmtF16>(lds, lds_e, tid);
         const long sn = s + gridDim.x;
-        if (sn < slabs) regs.load(mid_pay + row0(sn) * N, (long)N * N, mid_exp + row0(sn), N, tid);
+        if (sn < slabs) regs.template load<true>(mid_pay + row0(sn) * N, (long)N * N, mid_exp + row0(sn), N, tid);
         __syncthreads();
-        q16_fft_lds<N, S, N, T, 1, RS, MFMA>(lds, tw, tid);   // z: lines = x, elements along z (LDS rows)
-        q16_store_rows<N, N, RS, T, FMT_OUT>(lds, out_pay + row0(s) * N, (long)N * N, out_exp + row0(s), N, tid);
+        // z: lines = x, elements along z (LDS rows)
+        if constexpr (q16_wave_rows<N, T>()) {
+            q16_fft_lds<N, S, N, T, 1, RS, MFMA, true>(lds, tw, tid);
+            q16_last_stage_store<N, S, T, RS, FMT_OUT>(lds, tw, out_pay + row0(s) * N, N * N, out_exp + row0(s), N,
+                                                       tid);
+        } else {
+            q16_fft_lds<N, S, N, T, 1, RS, MFMA>(lds, tw, tid);
+            q16_store_rows<N, N, RS, T, FMT_OUT>(lds, out_pay + row0(s) * N, (long)N * N, out_exp + row0(s), N,
+                                                 tid);
+        }
     }
 }
 
