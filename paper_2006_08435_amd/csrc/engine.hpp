@@ -58,9 +58,7 @@ struct GlobAcc {
     __device__ __forceinline__ void store(int line, int e, float2 v) const { dst[(long)line * LS + (long)e * ES] = v; }
 };
 
-// Global memory with a runtime element stride and a per-thread line base
-// (the line index passed in is ignored; the caller has folded it into base).
-// Streaming (non-temporal) 8-byte global accesses: the data bypass the
+// Streaming (non-temporal) 8-byte global load: the data bypass the
 // retention policy of the caches.  Used only where measured to pay; see
 // stream_plane.
 __device__ __forceinline__ float2 ld_stream(const float2* p)
@@ -68,18 +66,18 @@ __device__ __forceinline__ float2 ld_stream(const float2* p)
     const unsigned long long u = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(p));
     return __builtin_bit_cast(float2, u);
 }
-__device__ __forceinline__ void st_stream(float2* p, float2 v)
-{
-    __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v), reinterpret_cast<unsigned long long*>(p));
-}
 
-// Whether the xy-plane passes of length n stream their plane loads and
-// stores.  Measured per length on batches of about 512 MB: for n = 125 and
-// 128 (planes 125 and 128 KB apart) streaming shortens the plane pass by
-// 4-8%; for n = 72 .. 120 it lengthens it by 4-12%, and for the z pass it
-// changes nothing, so everything else keeps the default policy.
+// Whether the xy-plane passes of length n stream their plane loads.
+// Measured per length on batches of about 512 MB: for n = 125 and 128
+// (planes 125 and 128 KB apart) streaming the loads and stores shortened
+// the plane pass by 4-8%; for n = 72 .. 120 it lengthened it by 4-12%.  The
+// stores keep the default policy after all: the z pass that follows reads
+// the last-written planes first (rev_tile) and finds them in the caches,
+// which is worth more (0.757 -> 0.731 ms per 32 x 128^3 inverse+forward).
 constexpr bool stream_plane(int n) { return n == 125 || n == 128; }
 
+// Global memory with a runtime element stride and a per-thread line base
+// (the line index passed in is ignored; the caller has folded it into base).
 struct GlobStrided {
     const float2* src;
     float2* dst;

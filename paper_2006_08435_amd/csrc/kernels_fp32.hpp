@@ -313,15 +313,14 @@ struct PlaneGeom {
 };
 
 // Global accessor for the y pass's final store: line = x, element = y.
-// COH: device-coherent (write-through) stores; NT: streaming stores.
-template <int N, bool COH = false, bool NT = false>
+// COH: device-coherent (write-through) stores.
+template <int N, bool COH = false>
 struct PlaneColOut {
     float2* p;
     __device__ __forceinline__ float2 load(int, int) const { return float2{}; }
     __device__ __forceinline__ void store(int x, int y, float2 v) const
     {
         if constexpr (COH) store_coherent(p + y * N + x, v);
-        else if constexpr (NT) st_stream(p + y * N + x, v);
         else p[y * N + x] = v;
     }
 };
@@ -359,7 +358,8 @@ k_plane(const float2* in, float2* out, const float2* __restrict__ tw)
 // SCALE: every input value at grid position r is first multiplied by the real
 // factor 2 * gE[0] * V[r] (V: one [nz][N][N] grid shared by the batch) -- the
 // prologue of the energy gradient.
-// NT: streaming plane loads and stores (see stream_plane).
+// NT: streaming plane loads (see stream_plane); the stores keep the default
+// policy so that the z pass after it finds their last part in the caches.
 template <int N, int S, bool SCALE = false, bool NT = false>
 __global__ void __launch_bounds__(PlaneGeom<N>::T)
 k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long planes, const float* __restrict__ V,
@@ -388,7 +388,7 @@ k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long pl
         }
         fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
         const LdsAcc<1, RS> col{lds};
-        const PlaneColOut<N, false, NT> dst{out + p * N * N};
+        const PlaneColOut<N> dst{out + p * N * N};
         run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
         __syncthreads();
     }
@@ -540,7 +540,7 @@ k_plane_pruned(const float2* in, float2* out, const float2* __restrict__ tw, lon
             const PlaneColOutBall<N> dst{out + plane_base(p), gz * gz, R2};
             run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
         } else {
-            const PlaneColOut<N, false, stream_plane(N)> dst{out + plane_base(p)};
+            const PlaneColOut<N> dst{out + plane_base(p)};
             run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
         }
         __syncthreads();
@@ -919,9 +919,18 @@ struct GlobZPacked {
     }
 };
 
+// Tile of this workgroup in the strided (z) passes, in reverse launch
+// order.  Workgroups start roughly in blockIdx order and the plane passes
+// run their planes in increasing order, so a z pass that takes the highest
+// tiles first begins on the data the plane pass before it wrote last (still
+// in the Infinity Cache) and ends on the lowest, where the plane pass after
+// it begins.  Measured on 32 x 128^3 inverse+forward: 0.757 -> 0.731 ms per
+// step, with the plane pass's stores left in the caches (default policy).
+__device__ __forceinline__ long rev_tile() { return (long)(gridDim.x - 1 - blockIdx.x); }
+
 // ENERGY: the pass is the last one of an inverse transform psi = IFFT(c);
 // while storing psi it accumulates sum V |psi|^2 and writes one FP64 partial
-// per workgroup to partials[blockIdx.x] (V indexed by position in the grid).
+// per tile to partials[tile] (V indexed by position in the grid).
 // PRUNE: 0 dense; 1 z pass of the pruned inverse, 2 z pass of the pruned
 // forward (GlobStridedPruned), 3 z pass of the pruned forward into a packed
 // sphere (GlobZPacked: `out` is the packed buffer, npts points per grid).
@@ -938,7 +947,8 @@ k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap
     static_assert(T % L == 0, "each thread keeps one line");
     __shared__ float2 lds[P::stages > 1 ? G::WORDS : 1];
     const int tid = threadIdx.x;
-    const long l0 = (long)blockIdx.x * L;
+    const long tile = rev_tile();
+    const long l0 = tile * L;
     const int myline = tid % L;
     const long li = l0 + myline;
     const int valid = (int)((m.lines - l0) < L ? (m.lines - l0) : L);
@@ -961,7 +971,7 @@ k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap
             run_tail<N, S, L, T, 1, false>(a, eg, tw, tid, valid);
         }
         const double t = block_sum<T>(eg.acc, red, tid);
-        if (tid == 0) partials[blockIdx.x] = t;
+        if (tid == 0) partials[tile] = t;
     } else if constexpr (PRUNE == 3) {
         const long o = li / m.nx;
         const int x = (int)(li - o * m.nx), y = (int)(o % m.odiv);
@@ -1009,7 +1019,7 @@ k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap
 
 // The energy pass without its output: the last pass of psi = IFFT(c), its
 // values only summed into sum V |psi|^2 (one FP64 partial per workgroup,
-// partials[blockIdx.x], the same products in the same order as the ENERGY
+// partials[tile], the same products in the same order as the ENERGY
 // form of k_axis_str) and never written.
 template <int N, int S, int L>
 __global__ void __launch_bounds__((AxisGeom<N, L>::T))
@@ -1023,7 +1033,8 @@ k_axis_energy(const float2* in, const float2* __restrict__ tw, AxisMap m, const 
     __shared__ float2 lds[P::stages > 1 ? G::WORDS : 1];
     __shared__ double red[T / 64];
     const int tid = threadIdx.x;
-    const long l0 = (long)blockIdx.x * L;
+    const long tile = rev_tile();
+    const long l0 = tile * L;
     const long li = l0 + tid % L;
     const int valid = (int)((m.lines - l0) < L ? (m.lines - l0) : L);
     long gbase = 0;
@@ -1043,7 +1054,7 @@ k_axis_energy(const float2* in, const float2* __restrict__ tw, AxisMap m, const 
         run_tail<N, S, L, T, 1, false>(a, eg, tw, tid, valid);
     }
     const double t = block_sum<T>(eg.acc, red, tid);
-    if (tid == 0) partials[blockIdx.x] = t;
+    if (tid == 0) partials[tile] = t;
 }
 
 // --------------------------------------------------------------- x rows --
@@ -1071,7 +1082,8 @@ k_axis_hloc(float2* buf, const float2* __restrict__ tw_inv, const float2* __rest
     __shared__ float2 lds[G::WORDS];
     __shared__ double red[T / 64];
     const int tid = threadIdx.x;
-    const long l0 = (long)blockIdx.x * L;
+    const long tile = rev_tile();
+    const long l0 = tile * L;
     const int myline = tid % L;
     const long li = l0 + myline;
     const int valid = (int)((m.lines - l0) < L ? (m.lines - l0) : L);
@@ -1114,7 +1126,7 @@ k_axis_hloc(float2* buf, const float2* __restrict__ tw_inv, const float2* __rest
         }
     }
     const double t = block_sum<T>(acc, red, tid);   // contains the barrier before the forward stages
-    if (tid == 0 && partials) partials[blockIdx.x] = t;
+    if (tid == 0 && partials) partials[tile] = t;
     // forward z-transform, stored in place
     if constexpr (P::stages == 1) {
         fft_stage<N, 0, -1, L, T, true, false>(a, dst, tw_fwd, tid, valid);
@@ -1149,7 +1161,8 @@ k_axis_density(const float2* buf, const float2* __restrict__ tw, AxisMap m, int 
     constexpr int R0 = P::radix(0), M0 = N / R0, NB0 = L * M0, IT0 = (NB0 + T - 1) / T;
     __shared__ float2 lds[G::WORDS];
     const int tid = threadIdx.x;
-    const long l0 = (long)blockIdx.x * L;
+    const long tile = rev_tile();
+    const long l0 = tile * L;
     const int myline = tid % L;
     const long li = l0 + myline;
     const int valid = (int)((m.lines - l0) < L ? (m.lines - l0) : L);
