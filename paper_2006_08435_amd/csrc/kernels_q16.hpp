@@ -346,8 +346,13 @@ k_q16_slab(const unsigned* mid_pay, const signed char* mid_exp, unsigned* out_pa
     __shared__ int lds_e[N];
     const int tid = threadIdx.x;
     Q16Regs<N, N, T> regs;
-    // row index of (b, z = 0, y); rows of successive z are N apart
-    auto row0 = [](long s) { return (s / N) * N * N + (s % N); };
+    // row index of (b, z = 0, y) of the k-th slab taken, rows of successive
+    // z N apart; slabs are taken in reverse (b, y) order, so the pass begins
+    // with the planes the plane pass wrote last (still in the caches)
+    auto row0 = [slabs](long k) {
+        const long s = slabs - 1 - k;
+        return (s / N) * N * N + (s % N);
+    };
     long s = blockIdx.x;
     if (s < slabs) regs.template load<true>(mid_pay + row0(s) * N, (long)N * N, mid_exp + row0(s), N, tid);
     for (; s < slabs; s += gridDim.x) {
