@@ -75,6 +75,10 @@ __device__ __forceinline__ float2 ld_stream(const float2* p)
 // the last-written planes first (rev_tile) and finds them in the caches,
 // which is worth more (0.757 -> 0.731 ms per 32 x 128^3 inverse+forward).
 constexpr bool stream_plane(int n) { return n == 125 || n == 128; }
+// Streaming loads pay on batches that do not stay in the caches between
+// passes; below this many bytes per pass (a single 128^3 grid is 16 MB) the
+// default policy is faster.
+constexpr long kStreamMinBytes = 32L << 20;
 
 // Global memory with a runtime element stride and a per-thread line base
 // (the line index passed in is ignored; the caller has folded it into base).

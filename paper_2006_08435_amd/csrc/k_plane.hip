@@ -11,11 +11,6 @@ static hipError_t launch_plane(const float2* in, float2* out, const float2* tw, 
     return hipGetLastError();
 }
 
-// Streaming plane accesses pay on batches that do not stay in the caches
-// between passes; below this many bytes per pass (a single 128^3 grid is
-// 16 MB) the default policy is faster.
-constexpr long kStreamMinBytes = 32L << 20;
-
 template <int N, int S>
 static hipError_t launch_plane_pf(const float2* in, float2* out, const float2* tw, long planes, int grid, int scale,
                                   const float* V, const double* gE, int nz, hipStream_t st)

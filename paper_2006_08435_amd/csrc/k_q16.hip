@@ -36,6 +36,16 @@ template <int N, int S, int F, bool M>
 static void plane_k(const unsigned* ip, const signed char* ie, unsigned* mp, signed char* me, const float2* tw,
                     long planes, hipStream_t st)
 {
+    // streaming input loads as in the FP32 plane pass (same lengths, passes
+    // of at least kStreamMinBytes of payload)
+    if constexpr (stream_plane(N)) {
+        if (planes * N * N * (long)sizeof(unsigned) >= kStreamMinBytes) {
+            const long grid = persistent_grid(&k_q16_plane<N, S, F, M, true>, Q16Geom<N>::T, planes);
+            hipLaunchKernelGGL((k_q16_plane<N, S, F, M, true>), dim3((unsigned)grid), dim3(Q16Geom<N>::T), 0, st, ip,
+                               ie, mp, me, tw, planes);
+            return;
+        }
+    }
     const long grid = persistent_grid(&k_q16_plane<N, S, F, M>, Q16Geom<N>::T, planes);
     hipLaunchKernelGGL((k_q16_plane<N, S, F, M>), dim3((unsigned)grid), dim3(Q16Geom<N>::T), 0, st, ip, ie, mp, me,
                        tw, planes);

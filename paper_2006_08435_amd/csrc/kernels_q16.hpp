@@ -78,8 +78,9 @@ struct Q16Regs {
     unsigned u[IT];
     int ev;
     // rows r at pay + r * rstride, exponents at ex[r * estride]; OFF32:
-    // 32-bit element offsets from pay (the tile spans < 2^32 elements)
-    template <bool OFF32 = false>
+    // 32-bit element offsets from pay (the tile spans < 2^32 elements); NT:
+    // streaming payload loads (see stream_plane)
+    template <bool OFF32 = false, bool NT = false>
     __device__ __forceinline__ void load(const unsigned* pay, long rstride, const signed char* ex, long estride,
                                          int tid)
     {
@@ -88,6 +89,7 @@ struct Q16Regs {
             const int i = tid + k * T;
             if (UNITS % T == 0 || i < UNITS) {
                 if constexpr (OFF32) u[k] = pay[(unsigned)((i / N) * rstride + (i % N))];
+                else if constexpr (NT) u[k] = __builtin_nontemporal_load(pay + (i / N) * rstride + (i % N));
                 else u[k] = pay[(i / N) * rstride + (i % N)];
             }
         }
@@ -301,8 +303,8 @@ __device__ __forceinline__ void q16_last_stage_store(const float2* lds, const fl
 
 // Pass A: planes p = b * N + z, persistent over `planes` with the next plane
 // prefetched into registers.  Rows of the input (b, z, y) -> rows of the FP16
-// intermediate (b, z, ky).
-template <int N, int S, int FMT_IN, bool MFMA>
+// intermediate (b, z, ky).  NT: streaming input loads.
+template <int N, int S, int FMT_IN, bool MFMA, bool NT = false>
 __global__ void __launch_bounds__(Q16Geom<N>::T)
 k_q16_plane(const unsigned* in_pay, const signed char* in_exp, unsigned* mid_pay, signed char* mid_exp,
             const float2* __restrict__ tw, long planes)
@@ -314,13 +316,13 @@ k_q16_plane(const unsigned* in_pay, const signed char* in_exp, unsigned* mid_pay
     const int tid = threadIdx.x;
     Q16Regs<N, N, T> regs;
     long p = blockIdx.x;
-    if (p < planes) regs.load(in_pay + p * N * N, N, in_exp + p * N, 1, tid);
+    if (p < planes) regs.template load<false, NT>(in_pay + p * N * N, N, in_exp + p * N, 1, tid);
     for (; p < planes; p += gridDim.x) {
         regs.put_exponent(lds_e, tid);
         __syncthreads();   // exponents visible; the previous plane is done with the tile
         regs.template to_lds<RS, FMT_IN>(lds, lds_e, tid);
         const long pn = p + gridDim.x;
-        if (pn < planes) regs.load(in_pay + pn * N * N, N, in_exp + pn * N, 1, tid);
+        if (pn < planes) regs.template load<false, NT>(in_pay + pn * N * N, N, in_exp + pn * N, 1, tid);
         __syncthreads();
         q16_fft_lds<N, S, N, T, RS, 1, MFMA>(lds, tw, tid);   // x: lines = rows
         if constexpr (q16_wave_rows<N, T>()) {                // y: lines = columns
