@@ -377,7 +377,7 @@ int fft3d_apply_potential(fft3d_plan_t plan, const void *c, const float *V, void
  * equal c, which is then overwritten).  Two passes: the inverse xy planes
  * into `work`, then one kernel per group of z-lines that runs the inverse
  * z transform of every orbital in turn and sums occ |psi|^2 in registers
- * (FP32, orbital order: deterministic), so psi is never stored.  With a
+ * (FP32, fixed orbital order: deterministic), so psi is never stored.  With a
  * cutoff on the plan, c must vanish outside the sphere and the pruned plane
  * pass is used.  Plans as for the energy entry points; returns the same
  * codes (FFT3D_E_ALIGNMENT: c / work not 16-byte, occ / rho not 4-byte

@@ -1143,7 +1143,7 @@ k_axis_hloc(float2* buf, const float2* __restrict__ tw_inv, const float2* __rest
 // adjacent z-lines of the grid (map: the lines of ONE grid) and loops over
 // the orbitals: stage 0 from HBM into LDS, the other stages in LDS, then each
 // thread adds occ[b] |psi|^2 at its fixed points in registers (FP32 FMA, in
-// orbital order: deterministic).  psi is never stored; rho ([z][y][x] real)
+// fixed orbital order, last first: deterministic).  psi is never stored; rho ([z][y][x] real)
 // is written once.  MODE 1 (cutoff R2): loads only of the planes with
 // Gz^2 < R2 (the others were not written by the pruned plane pass).
 template <int N, int L, int MODE>
@@ -1196,8 +1196,10 @@ k_axis_density(const float2* buf, const float2* __restrict__ tw, AxisMap m, int 
 #pragma unroll
     for (int k = 0; k < PER; ++k) acc[k] = 0.f;
     const LdsAcc<1, G::LP> a{lds};
-    if (batch > 0) load0(0);
-    for (int b = 0; b < batch; ++b) {
+    // orbitals from the last to the first: the plane pass before this one
+    // wrote the last orbitals last, so they are the ones still in the caches
+    if (batch > 0) load0(batch - 1);
+    for (int b = batch - 1; b >= 0; --b) {
 #pragma unroll
         for (int it = 0; it < IT0; ++it) {
             const int bb = tid + it * T, j = bb / L;
@@ -1208,7 +1210,7 @@ k_axis_density(const float2* buf, const float2* __restrict__ tw, AxisMap m, int 
             }
         }
         __syncthreads();
-        if (b + 1 < batch) load0(b + 1);
+        if (b > 0) load0(b - 1);
         if constexpr (P::stages > 1) {
             run_tail<N, 1, L, T, 1, false>(a, a, tw, tid, valid);
             __syncthreads();
