@@ -816,7 +816,8 @@ def bench_q16(args, prec):
         "plans": {"inverse": inv.describe()},
         "roofline": {"bound": "hbm", "achieved": round(alg / (passes[dom] * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(alg / (passes[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.workload, "%s<128, 1, %d, false>" % (
+                     # a prefix: the plane kernel's name carries one more template argument
+                     "traffic": measured_traffic(args.workload, "%s<128, 1, %d, false" % (
                          ["k_q16_plane", "k_q16_slab"][dom], 1 if prec == "fp16" else 2)),
                      "kernel": ["k_q16_plane", "k_q16_slab"][dom] + "<128,1>",
                      "ms_per_launch": round(passes[dom], 5)},
