@@ -67,14 +67,16 @@ __device__ __forceinline__ float2 ld_stream(const float2* p)
     return __builtin_bit_cast(float2, u);
 }
 
-// Whether the xy-plane passes of length n stream their plane loads.
-// Measured per length on batches of about 512 MB: for n = 125 and 128
-// (planes 125 and 128 KB apart) streaming the loads and stores shortened
-// the plane pass by 4-8%; for n = 72 .. 120 it lengthened it by 4-12%.  The
-// stores keep the default policy after all: the z pass that follows reads
-// the last-written planes first (rev_tile) and finds them in the caches,
-// which is worth more (0.757 -> 0.731 ms per 32 x 128^3 inverse+forward).
-constexpr bool stream_plane(int n) { return n == 125 || n == 128; }
+// Whether the xy-plane passes of length n stream their plane loads.  They
+// read each input plane once, and streaming those loads keeps the input out
+// of the Infinity Cache, which then still holds the plane pass's own output
+// (default-policy stores) when the z pass reads it, last-written first
+// (rev_tile).  Measured on whole inverse+forward steps over ~512 MB
+// batches: 2-7% faster at every length from 32 to 120 except 90 (no
+// change); 128 and 125 gain on the pass itself as well.  An earlier sweep
+// that timed the plane pass alone, with its stores streamed too, had found
+// lengths 72-120 slower: it could not see the effect on the z pass.
+constexpr bool stream_plane(int n) { return n >= 16; }
 // Streaming loads pay on batches that do not stay in the caches between
 // passes; below this many bytes per pass (a single 128^3 grid is 16 MB) the
 // default policy is faster.

@@ -373,7 +373,7 @@ static hipError_t run_pass(const fft3d_plan_s* p, const Pass& ps, const float2* 
     case Pass::kCubeK: return cube_fn(ps.n, S)(src, dst, tw, ps.count, st);
     case Pass::kPlaneK: return plane_fn(ps.n, S)(src, dst, tw, ps.count, st);
     case Pass::kPlanePfK:
-        return plane_pf_fn(ps.n, S)(src, dst, tw, ps.count, ps.grid, 0, nullptr, nullptr, 1, st);
+        return plane_pf_fn(ps.n, S)(src, dst, tw, ps.count, ps.grid, 0, nullptr, nullptr, 1, true, st);
     case Pass::kRowK: return axis_row_fn(ps.n, S)(src, dst, tw, ps.count, st);
     case Pass::kStrK: return axis_str_fn(ps.n, S)(src, dst, tw, ps.map, 0, nullptr, nullptr, 0, st);
     case Pass::kPlanePrunedK:
@@ -488,7 +488,7 @@ static hipError_t energy_transform(const fft3d_plan_s* p, int sign, const float2
     const float2* twx = p->d_tw + (same ? p->tw_x : p->tw_rx);
     const float2* twz = p->d_tw + (same ? p->tw_z : p->tw_rz);
     const long planes = (long)p->batch * nz;
-    hipError_t e = plane_pf_fn(n, sign)(src, dst, twx, planes, p->pf_grid, gE != nullptr, V, gE, nz, st);
+    hipError_t e = plane_pf_fn(n, sign)(src, dst, twx, planes, p->pf_grid, gE != nullptr, V, gE, nz, true, st);
     if (e != hipSuccess) return e;
     const AxisMap zmap{(long)p->batch * p->ny * n, n, p->ny, p->vol, (long)n, (long)n * p->ny};
     if (nz > 1 || epilogue) e = axis_str_fn(nz, sign)(dst, dst, twz, zmap, epilogue, V, p->partials, p->vol, st);
@@ -565,11 +565,13 @@ static hipError_t hloc_run(const fft3d_plan_s* p, const float2* c, float2* out, 
                                      0, st);
     } else {
         const long planes = (long)p->batch * nz;
-        e = plane_pf_fn(n, FFT3D_INVERSE)(c, out, twx_inv, planes, p->pf_grid, 0, nullptr, nullptr, nz, st);
+        e = plane_pf_fn(n, FFT3D_INVERSE)(c, out, twx_inv, planes, p->pf_grid, 0, nullptr, nullptr, nz, true, st);
         if (e == hipSuccess)
             e = axis_hloc_fn(nz)(out, twz_inv, twz_fwd, zmap, V, scale, mult, partials, p->vol, 0.0, 0, st);
         if (e == hipSuccess)
-            e = plane_pf_fn(n, FFT3D_FORWARD)(out, out, twx_fwd, planes, p->pf_grid, 0, nullptr, nullptr, nz, st);
+            // reads what the fused z kernel just wrote: no streaming
+            e = plane_pf_fn(n, FFT3D_FORWARD)(out, out, twx_fwd, planes, p->pf_grid, 0, nullptr, nullptr, nz, false,
+                                              st);
     }
     if (e == hipSuccess && E) e = launch_sum_partials(p->partials, p->n_partials, E, st);
     return e;
@@ -615,7 +617,8 @@ int fft3d_density(fft3d_plan_t p, const void* c, const float* occ, float* rho, v
         e = plane_pruned_fn(n, FFT3D_INVERSE)(src, w, twx, planes, grid, p->d_zlist, p->n_zlist, nz, p->cut_r2,
                                               nullptr, 0, st);
     } else {
-        e = plane_pf_fn(n, FFT3D_INVERSE)(src, w, twx, (long)p->batch * nz, p->pf_grid, 0, nullptr, nullptr, nz, st);
+        e = plane_pf_fn(n, FFT3D_INVERSE)(src, w, twx, (long)p->batch * nz, p->pf_grid, 0, nullptr, nullptr, nz, true,
+                                          st);
     }
     // the z-lines of one grid: (y, x) pairs, elements along z
     const AxisMap zmap{(long)p->ny * n, n, p->ny, p->vol, (long)n, (long)n * p->ny};

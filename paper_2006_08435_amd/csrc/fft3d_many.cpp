@@ -144,7 +144,7 @@ hipError_t launch_grouped(const fft3d_plan_s* p, const void* const* in, void* co
         const float2* src = static_cast<const float2*>(in[g]);
         float2* dst = static_cast<float2*>(out[g]);
         e = plane_pf_fn(n, p->direction)(src, dst, tw, planes, (int)(planes < resident ? planes : resident), 0,
-                                         nullptr, nullptr, n, st);
+                                         nullptr, nullptr, n, true, st);
         const long vol = (long)n * n * n;
         const AxisMap zmap{(long)mp.batch[g] * n * n, n, n, vol, (long)n, (long)n * n};
         if (e == hipSuccess && n > 1) e = axis_str_fn(n, p->direction)(dst, dst, tw, zmap, 0, nullptr, nullptr, 0, st);

@@ -13,11 +13,11 @@ static hipError_t launch_plane(const float2* in, float2* out, const float2* tw, 
 
 template <int N, int S>
 static hipError_t launch_plane_pf(const float2* in, float2* out, const float2* tw, long planes, int grid, int scale,
-                                  const float* V, const double* gE, int nz, hipStream_t st)
+                                  const float* V, const double* gE, int nz, bool stream, hipStream_t st)
 {
     const dim3 g((unsigned)grid), b(PlaneGeom<N>::T);
     if constexpr (stream_plane(N)) {
-        if (planes * N * N * (long)sizeof(float2) >= kStreamMinBytes) {
+        if (stream && planes * N * N * (long)sizeof(float2) >= kStreamMinBytes) {
             if (scale)
                 hipLaunchKernelGGL((k_plane_pf<N, S, true, true>), g, b, 0, st, in, out, tw, planes, V, gE, nz);
             else

@@ -14,8 +14,10 @@ struct SphereRow;
 using CubeFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long grids, hipStream_t st);
 using PlaneFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, hipStream_t st);
 // scale != 0: fused prologue, input at r multiplied by 2 gE[0] V[r].
+// stream: the input is cold (not just written by the pass before), so its
+// loads may stream (stream_plane, kStreamMinBytes).
 using PlanePfFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, int grid, int scale,
-                                 const float* V, const double* gE, int nz, hipStream_t st);
+                                 const float* V, const double* gE, int nz, bool stream, hipStream_t st);
 // energy != 0: fused epilogue, V[r]|out(r)|^2 summed into one FP64 partial
 // per workgroup (axis_str_blocks(m) of them) at `partials`; energy == 2: the
 // sum only, `out` is not written.
