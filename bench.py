@@ -35,7 +35,7 @@ WORKLOADS = {
     "big256": (256, 4, 6000, "c2c 3D FFT, 4 grids of 256^3 (three-pass form), inverse then forward, complex64"),
     "big512": (512, 1, 6100, "c2c 3D FFT, one 512^3 grid (three-pass form), inverse then forward, complex64"),
 }
-EXTRA_WORKLOADS = ("mixed", "energy96", "fp16_128", "bf16_128", "pruned128", "real128")
+EXTRA_WORKLOADS = ("mixed", "energy96", "fp16_128", "bf16_128", "pruned128", "real128", "copy_sweep")
 
 
 def source_hash() -> str:
@@ -96,6 +96,8 @@ def main(argv=None):
     import paper_2006_08435_amd as fft3d
     from paper_2006_08435_amd import _lib
 
+    if args.workload == "copy_sweep":
+        return bench_copy_sweep(args)
     if args.workload == "mixed":
         return bench_mixed(args)
     if args.workload == "energy96":
@@ -131,46 +133,37 @@ def main(argv=None):
         inv.exec_ptr(a.data_ptr(), b.data_ptr(), sh)
         fwd.exec_ptr(b.data_ptr(), c.data_ptr(), sh)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / args.steps
+    # One step as its kernel launches: the passes of the inverse (a -> b,
+    # then in place on b) and of the forward (b -> c, then in place on c);
+    # running them in order is exactly the two fft3d_exec calls of step().
+    seq = []
+    for name, plan, src, dst in (("inverse", inv, a, b), ("forward", fwd, b, c)):
+        for k in range(L.fft3d_plan_passes(plan.handle)):
+            seq.append((name, k, plan.handle, (src if k == 0 else dst).data_ptr(), dst.data_ptr()))
+    # Timed region: K steps through fft3d_exec, HIP events on the launch
+    # stream around them (after W warm-up steps).
+    ms_step = _time(step, args.steps, args.warmup, stream)
     print("[bench] %d steps, %.4f ms/step" % (args.steps, ms_step), file=sys.stderr, flush=True)
+    # Kernel durations: K more steps as their individual launches, with a HIP
+    # event on the same stream before the first launch and after every
+    # launch (the events between launches cost ~2% of the step time, so the
+    # step time above is taken without them).
+    launch_fns = [(lambda h=h, k=k, s_=s_, d_=d_: _lib.check(L.fft3d_exec_pass(h, k, s_, d_, sh)))
+                  for _, k, h, s_, d_ in seq]
+    ms_events, launch_ms = timed_launches(launch_fns, args.steps, 0, stream)
 
     # The same steps timed one by one; where the working set would stay in
     # the 256 MB Infinity Cache, also cold: a 512 MiB streaming copy (untimed)
     # evicts it before each step.
-    timing = {"warm": step_distribution(step, args.steps, stream), "cold": None}
+    timing = {"warm": step_distribution(step, args.steps, stream), "cold": None,
+              "ms_per_step_with_launch_events": round(ms_events, 5)}
     if a.numel() * 8 <= 64 << 20:
         f0 = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
         f1 = torch.empty_like(f0)
         timing["cold"] = step_distribution(step, args.steps, stream,
                                            flush=lambda: fft3d.stream_copy(f0, f1, stream))
         del f0, f1
-
-    # Per-kernel average launch durations (HIP events on the launch stream).
-    passes = []
-    for name, plan, src, dst in (("inverse", inv, a, b), ("forward", fwd, b, c)):
-        for k in range(L.fft3d_plan_passes(plan.handle)):
-            for _ in range(3):
-                _lib.check(L.fft3d_exec_pass(plan.handle, k, src.data_ptr(), dst.data_ptr(), sh))
-            reps = max(10, args.steps)
-            s0 = torch.cuda.Event(enable_timing=True)
-            s1 = torch.cuda.Event(enable_timing=True)
-            s0.record(stream)
-            for _ in range(reps):
-                _lib.check(L.fft3d_exec_pass(plan.handle, k, src.data_ptr(), dst.data_ptr(), sh))
-            s1.record(stream)
-            torch.cuda.synchronize()
-            passes.append({"transform": name, "pass": k, "ms": s0.elapsed_time(s1) / reps})
-    # restore b, c from a (the pass loops above overwrote them)
+    passes = [{"transform": name, "pass": k, "ms": ms} for (name, k, _, _, _), ms in zip(seq, launch_ms)]
     step()
     torch.cuda.synchronize()
 
@@ -192,17 +185,26 @@ def main(argv=None):
     bytes_per_transform = 16.0 * n ** 3 * batch
     hbm_gbs = 2 * bytes_per_transform / (ms_step * 1e-3) / 1e9
 
-    # dominant kernel: largest average launch duration
-    dom = max(passes, key=lambda p: p["ms"])
-    kernel_list = inv.describe().split("kernels=")[1].split(",")
-    dom_name = kernel_list[dom["pass"]]
-    achieved = bytes_per_transform / (dom["ms"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.workload, "%s<%d, %s" % (
-                    dom_name, n, "-1" if dom["transform"] == "forward" else "1")),
-                "kernel": "%s<%d,%s>" % (dom_name, n, "-1" if dom["transform"] == "forward" else "1"),
-                "ms_per_launch": round(dom["ms"], 5)}
+    # Roofline unit: one transform (one read of its input, one write of its
+    # output, 16 B per point), over the summed average durations of its
+    # kernels; the slower of the two transforms is reported.
+    kernel_names = {name: plan.describe().split("kernels=")[1].split(",")
+                    for name, plan in (("inverse", inv), ("forward", fwd))}
+    sgn = {"inverse": "1", "forward": "-1"}
+    per_transform = {}
+    for p_ in passes:
+        per_transform.setdefault(p_["transform"], []).append(p_)
+    slow = max(per_transform, key=lambda t: sum(p_["ms"] for p_ in per_transform[t]))
+    t_ms = sum(p_["ms"] for p_ in per_transform[slow])
+    kerns = ["%s<%d, %s" % (kernel_names[slow][p_["pass"]], n, sgn[slow]) for p_ in per_transform[slow]]
+    dom = max(passes, key=lambda p_: p_["ms"])
+    roofline = transform_roofline(
+        bytes_per_transform, t_ms, "%s transform: %s" % (slow, " + ".join("%s>" % k for k in kerns)),
+        traffic_sum(args.workload, kerns), launches=len(kerns),
+        dominant_pass={"kernel": "%s<%d,%s>" % (kernel_names[dom["transform"]][dom["pass"]], n,
+                                                sgn[dom["transform"]]),
+                       "ms": round(dom["ms"], 5),
+                       "gbs_own_bytes": round(bytes_per_transform / (dom["ms"] * 1e-3) / 1e9, 1)})
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -271,6 +273,46 @@ def _time(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
+def timed_launches(seq, steps, warmup, stream):
+    """Time `steps` repetitions of a launch sequence (a list of callables,
+    each enqueueing one kernel) with a HIP event on `stream` before the
+    first launch and after every launch.  Returns (ms per repetition,
+    [average ms of each launch])."""
+    import torch
+    for _ in range(warmup):
+        for f in seq:
+            f()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(seq) + 1)] for _ in range(steps)]
+    for e in evs:
+        e[0].record(stream)
+        for i, f in enumerate(seq):
+            f()
+            e[i + 1].record(stream)
+    torch.cuda.synchronize()
+    total = evs[0][0].elapsed_time(evs[-1][-1]) / steps
+    return total, [sum(e[i].elapsed_time(e[i + 1]) for e in evs) / steps for i in range(len(seq))]
+
+
+def transform_roofline(alg_bytes, ms, kernel, traffic=None, **extra):
+    """HBM roofline of one transform: its algorithmic bytes (one read of the
+    input, one write of the output) over the summed average durations of
+    its kernels, against 8 TB/s; traffic = counter-measured HBM bytes of the
+    same kernels, traffic_ratio = traffic / algorithmic bytes."""
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+         "traffic_ratio": None if traffic is None else round(traffic / alg_bytes, 3),
+         "kernel": kernel, "algorithmic_bytes": alg_bytes, "ms_per_launch": round(ms, 5)}
+    r.update(extra)
+    return r
+
+
+def traffic_sum(workload, kernels):
+    t = [measured_traffic(workload, k) for k in kernels]
+    return None if any(v is None for v in t) else sum(t)
+
+
 def copy_peak_gbs(nbytes, reps=20):
     """Practical HBM ceiling: GB/s (read + write) of the library's streaming
     copy (fft3d_stream_copy) of an nbytes buffer into another."""
@@ -332,6 +374,39 @@ def _many_kernels(desc):
         return "hybrid: k_plane_pf + k_axis_str for %s, k_many<1,%s> for the other groups" % (
             desc.split("grouped=")[1].split()[0], desc.split("threads=")[1].split()[0])
     return "grouped: k_plane_pf + k_axis_str per group"
+
+
+def bench_copy_sweep(args):
+    """Device-to-device copy rate (read + write bytes per second) against the
+    buffer size, for the library's streaming copy (non-temporal 16-byte
+    loads and stores) and for torch's copy kernel (default cache policy).
+    Source plus destination below the 256 MB Infinity Cache are served from
+    it after the first repetition; above it every byte goes to HBM.  This is
+    the indirect evidence of the cache's bandwidth: no counter of it is
+    exposed on gfx950."""
+    import torch
+    import paper_2006_08435_amd as fft3d
+    stream = torch.cuda.current_stream()
+    rows = []
+    for mib in (8, 16, 32, 64, 128, 256, 512, 1024):
+        src = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        reps = max(20, min(400, (4096 // mib)))
+        ms_nt = _time(lambda: fft3d.stream_copy(src, dst, stream), reps, 5, stream)
+        ms_tc = _time(lambda: dst.copy_(src), reps, 5, stream)
+        rows.append({"mib_each": mib, "src_plus_dst_mib": 2 * mib, "reps": reps,
+                     "stream_copy_gbs": round(2 * (mib << 20) / (ms_nt * 1e-3) / 1e9, 1),
+                     "torch_copy_gbs": round(2 * (mib << 20) / (ms_tc * 1e-3) / 1e9, 1)})
+        del src, dst
+        print("[bench] copy %d MiB done" % mib, file=sys.stderr, flush=True)
+    best = max(r["stream_copy_gbs"] for r in rows)
+    rec = _base_record(best, "GB/s", args, 0.0, "device copy rate against buffer size",
+                       {"sizes_mib": [r["mib_each"] for r in rows]}, dtype="bytes")
+    rec.update({"metric": "device-to-device copy GB/s (read + write)", "rows": rows,
+                "roofline": None, "cpu_baseline": None})
+    print(json.dumps(rec))
+    return 0
 
 
 def bench_mixed(args):
@@ -407,11 +482,9 @@ def bench_mixed(args):
                        "per_group_batched_launches_6": round(group_ms, 4),
                        "hybrid_1024x2_eager": round(hybrid_ms, 4)},
         "plans": {"many_tuned": plan.describe(), "many_default": persistent_desc, "many_hybrid": hyb.describe()},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("mixed", "k_many") if "mode=persistent" in plan.describe() else None,
-                     "kernel": _many_kernels(plan.describe()),
-                     "ms_per_exec": round(graph_ms, 5)},
+        "roofline": transform_roofline(
+            bytes_, graph_ms, _many_kernels(plan.describe()),
+            measured_traffic("mixed", "k_many") if "mode=persistent" in plan.describe() else None),
         "cpu_baseline": None if args.no_cpu_baseline else _cpu_oracle(xs[0], 64, 1, args.cpu_seconds, "64^3 grids"),
         "source_hash": source_hash(),
     })
@@ -524,10 +597,13 @@ def bench_energy(args):
         "rel_l2_vs_fp64": {"E_rel": abs(E.item() - E_all) / abs(E_all),
                            "grad_first8": float(np.linalg.norm(g8 - g_ref) / np.linalg.norm(g_ref)),
                            "E_only_rel": abs(E_only_value - E_all) / abs(E_all)},
-        "roofline": {"bound": "hbm", "achieved": round(alg / (fwd_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(alg / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "energy_fwd (k_plane_pf + k_axis_str<ENERGY>)",
-                     "ms_per_launch": round(fwd_ms, 5)},
+        # unit: the energy forward (one read of c, one write of psi; V, 3.4 MB,
+        # and the partial sums are not counted)
+        "roofline": transform_roofline(alg, fwd_ms, "energy_fwd: k_plane_pf<96, 1, false, true> + "
+                                       "k_axis_str<96, 1, 64, true, 0> + k_sum_partials",
+                                       traffic_sum("energy96", ["k_plane_pf<96, 1, false, true",
+                                                                "k_axis_str<96, 1, 64, true, 0"]),
+                                       launches=3),
         "cpu_baseline": None if args.no_cpu_baseline else _cpu_oracle(c, n, 1, args.cpu_seconds, "96^3 orbitals"),
         "source_hash": source_hash(),
     })
@@ -579,21 +655,22 @@ def bench_pruned(args):
         _lib.check(L.fft3d_exec_packed(plans["inverse"].handle, work.data_ptr(), packed_c.data_ptr(), sh))
         _lib.check(L.fft3d_exec_packed(plans["forward"].handle, work.data_ptr(), packed_back.data_ptr(), sh))
 
-    pruned_ms = _time(pruned_step, args.steps, args.warmup, stream)
     dense_ms = _time(dense_step, args.steps, args.warmup, stream)
     packed_ms = _time(packed_step, args.steps, args.warmup, stream)
-    times = {}
+    # the pruned step as its four launches, each bracketed by HIP events
+    names, seq = [], []
     for name, src, dst in (("inverse", xt, psi), ("forward", psi, back)):
         pl = plans[name]
-        times[name] = _time(lambda: pl.exec_ptr(src.data_ptr(), dst.data_ptr(), sh), args.steps, args.warmup,
-                            stream)
+        for k in range(L.fft3d_plan_passes(pl.handle)):
+            names.append("%s_pass%d" % (name, k))
+            seq.append(lambda h=pl.handle, k=k, s_=(src if k == 0 else dst).data_ptr(), d_=dst.data_ptr():
+                       _lib.check(L.fft3d_exec_pass(h, k, s_, d_, sh)))
+    pruned_ms = _time(pruned_step, args.steps, args.warmup, stream)
+    pruned_events_ms, per = timed_launches(seq, args.steps, 0, stream)
+    times = dict(zip(names, per))
+    for name, src in (("inverse", xt), ("forward", psi)):
         times["dense_" + name] = _time(lambda: plans["dense_" + name].exec_ptr(src.data_ptr(), d_back.data_ptr(),
                                                                                sh), args.steps, args.warmup, stream)
-        for k in range(L.fft3d_plan_passes(pl.handle)):
-            s_ = src if k == 0 else dst
-            times["%s_pass%d" % (name, k)] = _time(
-                lambda: _lib.check(L.fft3d_exec_pass(pl.handle, k, s_.data_ptr(), dst.data_ptr(), sh)),
-                args.steps, args.warmup, stream)
     pruned_step()
     dense_step()
     packed_step()
@@ -614,45 +691,47 @@ def bench_pruned(args):
         worst["round_trip_inside_sphere"] = max(worst["round_trip_inside_sphere"],
                                                 float(np.linalg.norm(rt - x[j][sphere]) /
                                                       np.linalg.norm(x[j][sphere])))
-    # algorithmic bytes per grid of each pruned pass
+    # algorithmic bytes: the inverse reads the sphere's coefficients and
+    # writes the whole grid, the forward reads the whole grid and writes the
+    # sphere's coefficients
     zin = (g * g) < r2
     disk = int(((g[:, None] ** 2 + g[None, :] ** 2) < r2).sum())   # x-rows (inverse) = z-lines (forward)
     nzp, nsph = int(zin.sum()), int(sphere.sum())
+    alg = 8.0 * (nsph + n ** 3) * B
+    # bytes the pruned passes must move at least (whole rows / lines as the
+    # passes fetch them, the intermediate included)
     pass_bytes = {"inverse_pass0": 8.0 * (disk * n + nzp * n * n) * B,
                   "inverse_pass1": 8.0 * (nzp * n * n + n ** 3) * B,
                   "forward_pass0": 8.0 * (n ** 3 + disk * n) * B,
                   "forward_pass1": 8.0 * (disk * n + nsph) * B}
-    total = sum(pass_bytes.values())
     flops = 2 * 5.0 * n ** 3 * math.log2(n ** 3) * B
     rec = _base_record(flops / (pruned_ms * 1e-3) / 1e9, "GFLOP/s", args, pruned_ms,
                        "pruned c2c 3D FFT, sphere-cutoff coefficients (|G| < N/4), 32 grids of 128^3: inverse then "
                        "forward, complex64; GFLOP/s counts the dense 5N^3log2N^3 per transform",
                        {"n": n, "batch": B, "cutoff_r2": r2, "precision": "fp32",
                         "input": "sphere-cutoff plane-wave coefficients"})
-    pk = [k for k in pass_bytes]
-    dom = max(pk, key=lambda k: times[k])
-    achieved = pass_bytes[dom] / (times[dom] * 1e-3) / 1e9
-    kern = {"inverse_pass0": "k_plane_pruned<128, 1, 0, false>", "inverse_pass1": "k_axis_str<128, 1, 64, false, 1>",
-            "forward_pass0": "k_plane_pruned<128, -1, 1, false>",
-            "forward_pass1": "k_axis_str<128, -1, 64, false, 2>"}
+    kern = {"inverse": ["k_plane_pruned<128, 1, 0, false", "k_axis_str<128, 1, 64, false, 1"],
+            "forward": ["k_plane_pruned<128, -1, 1, false", "k_axis_str<128, -1, 64, false, 2"]}
+    t_ms = {t: times[t + "_pass0"] + times[t + "_pass1"] for t in ("inverse", "forward")}
+    slow = max(t_ms, key=t_ms.get)
     rec.update({
         "times_ms": dict({"pruned_step": round(pruned_ms, 4), "dense_step": round(dense_ms, 4),
                           "speedup": round(dense_ms / pruned_ms, 3),
-                          "packed_step": round(packed_ms, 4)},
+                          "packed_step": round(packed_ms, 4),
+                          "pruned_step_with_launch_events": round(pruned_events_ms, 4)},
                          **{k: round(v, 4) for k, v in times.items()}),
         "sphere": {"nonzero_planes": nzp, "disk_lines_per_grid": disk, "sphere_points_per_grid": nsph,
                    "points_per_grid": n ** 3},
-        "algorithmic_bytes": {"pruned_step": total, "dense_step": 2 * 2 * 2 * 8.0 * n ** 3 * B,
-                              "per_pass": pass_bytes},
-        "hbm_gbs_algorithmic": round(total / (pruned_ms * 1e-3) / 1e9, 1),
+        "algorithmic_bytes": {"per_transform": alg, "dense_transform": 16.0 * n ** 3 * B,
+                              "pass_minimum": pass_bytes},
+        "hbm_gbs_algorithmic": round(2 * alg / (pruned_ms * 1e-3) / 1e9, 1),
+        "hbm_frac_algorithmic": round(2 * alg / (pruned_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "vs_dense_plans": equal,
         "packed": {"points_per_grid": npts, "round_trip_max_abs_err_over_max": packed_rt},
         "rel_l2_vs_fp64": dict(worst, sampled=[0, B - 1]),
         "plans": {k: v.describe() for k, v in plans.items()},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("pruned128", kern[dom]),
-                     "kernel": kern[dom], "pass": dom, "ms_per_launch": round(times[dom], 5)},
+        "roofline": transform_roofline(alg, t_ms[slow], "%s transform: %s" % (slow, " + ".join(
+            k + ">" for k in kern[slow])), traffic_sum("pruned128", kern[slow]), launches=2),
         "cpu_baseline": None if args.no_cpu_baseline else _cpu_oracle(x, n, 1, args.cpu_seconds, "128^3 grids"),
         "source_hash": source_hash(),
     })
@@ -684,16 +763,18 @@ def bench_real(args):
         _lib.check(L.fft3d_exec(fwd.handle, ft.data_ptr(), half.data_ptr(), sh))
         _lib.check(L.fft3d_exec(inv.handle, half.data_ptr(), back.data_ptr(), sh))
 
-    ms = _time(step, args.steps, args.warmup, stream)
-    times = {}
     # (buffers per pass: r2c = [plane ft -> half, z in place on half];
     #  c2r = [z in place on half, plane half -> back])
+    names, seq = [], []
     for name, pl, bufs in (("r2c", fwd, ((ft, half), (half, half))), ("c2r", inv, ((half, half), (half, back)))):
         for k in range(L.fft3d_plan_passes(pl.handle)):
             a_, b_ = bufs[k]
-            times["%s_pass%d" % (name, k)] = _time(
-                lambda: _lib.check(L.fft3d_exec_pass(pl.handle, k, a_.data_ptr(), b_.data_ptr(), sh)),
-                args.steps, args.warmup, stream)
+            names.append("%s_pass%d" % (name, k))
+            seq.append(lambda h=pl.handle, k=k, s_=a_.data_ptr(), d_=b_.data_ptr():
+                       _lib.check(L.fft3d_exec_pass(h, k, s_, d_, sh)))
+    ms = _time(step, args.steps, args.warmup, stream)   # the step through fft3d_exec
+    ms_events, per = timed_launches(seq, args.steps, 0, stream)
+    times = dict(zip(names, per))
     # the timing loop above left `half` transformed in place: recompute and check
     _lib.check(L.fft3d_exec(fwd.handle, ft.data_ptr(), half.data_ptr(), sh))
     torch.cuda.synchronize()
@@ -709,28 +790,27 @@ def bench_real(args):
         worst["round_trip"] = max(worst["round_trip"],
                                   float(np.linalg.norm(bk[j] / n ** 3 - f[j]) / np.linalg.norm(f[j])))
     real_b, half_b = 4.0 * n ** 3, 8.0 * n * n * h
-    pass_bytes = {"r2c_pass0": (real_b + half_b) * B, "r2c_pass1": 2 * half_b * B,
-                  "c2r_pass0": 2 * half_b * B, "c2r_pass1": (half_b + real_b) * B}
-    total = sum(pass_bytes.values())
+    # algorithmic bytes of each transform: its input read once, its output
+    # written once (the real grid and the half spectrum)
+    alg = (real_b + half_b) * B
     flops = 2 * 2.5 * n ** 3 * math.log2(n ** 3) * B
     rec = _base_record(flops / (ms * 1e-3) / 1e9, "GFLOP/s", args, ms,
                        "real 3D FFT, 32 real grids of 128^3: r2c then c2r, float32 / complex64 half spectra; "
                        "GFLOP/s counts 2.5 N^3 log2 N^3 per real transform",
                        {"n": n, "batch": B, "precision": "fp32", "input": "uniform real grids"})
-    dom = max(pass_bytes, key=lambda k: times[k])
-    achieved = pass_bytes[dom] / (times[dom] * 1e-3) / 1e9
-    kern = {"r2c_pass0": "k_plane_r2c<128, -1>", "r2c_pass1": "k_axis_str<128, -1, 64, false, 0>",
-            "c2r_pass0": "k_axis_str<128, 1, 64, false, 0>", "c2r_pass1": "k_plane_c2r<128, 1>"}
+    kern = {"r2c": ["k_plane_r2c<128, -1", "k_axis_str<128, -1, 64, false, 0"],
+            "c2r": ["k_axis_str<128, 1, 64, false, 0", "k_plane_c2r<128, 1"]}
+    t_ms = {t: times[t + "_pass0"] + times[t + "_pass1"] for t in ("r2c", "c2r")}
+    slow = max(t_ms, key=t_ms.get)
     rec.update({
-        "times_ms": {k: round(v, 4) for k, v in times.items()},
-        "algorithmic_bytes": dict({"step": total}, **pass_bytes),
-        "hbm_gbs_algorithmic": round(total / (ms * 1e-3) / 1e9, 1),
-        "hbm_frac_algorithmic": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "times_ms": dict({k: round(v, 4) for k, v in times.items()}, step_with_launch_events=round(ms_events, 4)),
+        "algorithmic_bytes_per_transform": alg,
+        "hbm_gbs_algorithmic": round(2 * alg / (ms * 1e-3) / 1e9, 1),
+        "hbm_frac_algorithmic": round(2 * alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "rel_l2_vs_fp64": dict(worst, sampled=[0, B - 1]),
         "plans": {"r2c": fwd.describe(), "c2r": inv.describe()},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("real128", kern[dom]),
-                     "kernel": kern[dom], "pass": dom, "ms_per_launch": round(times[dom], 5)},
+        "roofline": transform_roofline(alg, t_ms[slow], "%s transform: %s" % (slow, " + ".join(
+            k + ", ...>" for k in kern[slow])), traffic_sum("real128", kern[slow]), launches=2),
         "cpu_baseline": None,
         "source_hash": source_hash(),
     })
@@ -740,7 +820,7 @@ def bench_real(args):
 
 def bench_q16(args, prec):
     """32 x 128^3 in scaled 16-bit storage: inverse then forward, against the
-    FP32 path on the same (dequantized) data."""
+    FP32 path on the same (dequantized) data; both radix-16 engines."""
     import numpy as np
     import torch
     import oracle
@@ -752,26 +832,62 @@ def bench_q16(args, prec):
     qa = fft3d.quantize(xt, prec)
     qb = torch.empty_like(qa)
     qc = torch.empty_like(qa)
-    inv = fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_INVERSE)
-    fwd = fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_FORWARD)
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
     L = _lib.lib()
-    step = lambda: (inv.exec_ptr(qa.data_ptr(), qb.data_ptr(), sh), fwd.exec_ptr(qb.data_ptr(), qc.data_ptr(), sh))
-    ms = _time(step, args.steps, args.warmup, stream)
-    passes = []
-    for k in range(L.fft3d_plan_passes(inv.handle)):
-        src, dst = (qa, qb) if k == 0 else (qb, qb)
-        t = _time(lambda: _lib.check(L.fft3d_exec_pass(inv.handle, k, src.data_ptr(), dst.data_ptr(), sh)),
-                  max(10, args.steps), 3, stream)
-        passes.append(t)
-    # the same step with the radix-16 stage on the matrix cores (FFT3D_Q16_MFMA=1 at plan time)
-    os.environ["FFT3D_Q16_MFMA"] = "1"
-    inv_m = fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_INVERSE)
-    fwd_m = fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_FORWARD)
-    del os.environ["FFT3D_Q16_MFMA"]
+
+    def plans(mfma):
+        # the radix-16 engine is chosen at plan time (FFT3D_Q16_MFMA=1: matrix cores)
+        if mfma:
+            os.environ["FFT3D_Q16_MFMA"] = "1"
+        try:
+            return (fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_INVERSE),
+                    fft3d.Plan(n, n, n, B, prec, fft3d.FFT3D_FORWARD))
+        finally:
+            os.environ.pop("FFT3D_Q16_MFMA", None)
+
+    def launches(inv, fwd):
+        seq = []
+        for h, src, dst in ((inv.handle, qa, qb), (fwd.handle, qb, qc)):
+            for k in range(L.fft3d_plan_passes(h)):
+                seq.append(lambda h=h, k=k, s_=(src if k == 0 else dst).data_ptr(), d_=dst.data_ptr():
+                           _lib.check(L.fft3d_exec_pass(h, k, s_, d_, sh)))
+        return seq
+
+    fmt = oracle.FMT_FP16 if prec == "fp16" else oracle.FMT_BF16
+    nb = 4 * n ** 3 * B
+    dec = lambda r, j: oracle.q16_decode(r[:nb].view(np.uint16).reshape(B, n, n, n, 2)[j:j + 1],
+                                          r[nb:].view(np.int8).reshape(B, n, n)[j:j + 1], fmt)
+
+    def errors(inv, fwd):
+        """rel-L2 of this engine's inverse (vs FP64 on the dequantized input
+        and on the original FP32 input) and forward, sampled grids."""
+        inv.exec_ptr(qa.data_ptr(), qb.data_ptr(), sh)
+        fwd.exec_ptr(qb.data_ptr(), qc.data_ptr(), sh)
+        torch.cuda.synchronize()
+        raw = {k: v.cpu().numpy() for k, v in (("a", qa), ("b", qb), ("c", qc))}
+        e_inv, e_fwd, e_orig = [], [], []
+        for j in (0, 16, 31):
+            xin = dec(raw["a"], j)
+            psi = dec(raw["b"], j)
+            ri = oracle.fft3d(xin, 1)
+            e_inv.append(float(np.linalg.norm(psi - ri) / np.linalg.norm(ri)))
+            ref_orig = oracle.fft3d(x[j:j + 1].astype(np.complex128), 1)
+            e_orig.append(float(np.linalg.norm(psi - ref_orig) / np.linalg.norm(ref_orig)))
+            rf = oracle.fft3d(psi, -1)
+            e_fwd.append(float(np.linalg.norm(dec(raw["c"], j) - rf) / np.linalg.norm(rf)))
+        return {"inverse_vs_dequantized_input_max": max(e_inv), "forward_max": max(e_fwd),
+                "inverse_vs_original_fp32_input_max": max(e_orig), "grids": [0, 16, 31]}
+
+    inv, fwd = plans(False)
+    inv_m, fwd_m = plans(True)
+    # step times through fft3d_exec, then the launches with events between them
+    ms = _time(lambda: (inv.exec_ptr(qa.data_ptr(), qb.data_ptr(), sh), fwd.exec_ptr(qb.data_ptr(), qc.data_ptr(), sh)),
+               args.steps, args.warmup, stream)
     ms_mfma = _time(lambda: (inv_m.exec_ptr(qa.data_ptr(), qb.data_ptr(), sh),
                              fwd_m.exec_ptr(qb.data_ptr(), qc.data_ptr(), sh)), args.steps, args.warmup, stream)
+    _, per_launch = timed_launches(launches(inv, fwd), args.steps, args.warmup, stream)
+    _, per_launch_m = timed_launches(launches(inv_m, fwd_m), args.steps, args.warmup, stream)
     # FP32 reference path on the dequantized input, same step
     xd = fft3d.dequantize(qa, x.shape, prec)
     b32, c32 = torch.empty_like(xd), torch.empty_like(xd)
@@ -779,23 +895,8 @@ def bench_q16(args, prec):
     fwd32 = fft3d.Plan(n, n, n, B, "fp32", fft3d.FFT3D_FORWARD)
     ms32 = _time(lambda: (inv32.exec_ptr(xd.data_ptr(), b32.data_ptr(), sh),
                           fwd32.exec_ptr(b32.data_ptr(), c32.data_ptr(), sh)), args.steps, args.warmup, stream)
-    step()
-    torch.cuda.synchronize()
-    fmt = oracle.FMT_FP16 if prec == "fp16" else oracle.FMT_BF16
-    nb = 4 * n ** 3 * B
-    raw = {k: v.cpu().numpy() for k, v in (("a", qa), ("b", qb), ("c", qc))}
-    dec = lambda r, j: oracle.q16_decode(r[:nb].view(np.uint16).reshape(B, n, n, n, 2)[j:j + 1],
-                                          r[nb:].view(np.int8).reshape(B, n, n)[j:j + 1], fmt)
-    e_inv, e_fwd, e_orig = [], [], []
-    for j in (0, 16, 31):
-        xin = dec(raw["a"], j)
-        psi = dec(raw["b"], j)
-        e_inv.append(float(np.linalg.norm(psi - oracle.fft3d(xin, 1)) / np.linalg.norm(oracle.fft3d(xin, 1))))
-        ref_orig = oracle.fft3d(x[j:j + 1].astype(np.complex128), 1)
-        e_orig.append(float(np.linalg.norm(psi - ref_orig) / np.linalg.norm(ref_orig)))
-        back = dec(raw["c"], j)
-        rf = oracle.fft3d(psi, -1)
-        e_fwd.append(float(np.linalg.norm(back - rf) / np.linalg.norm(rf)))
+    err_m = errors(inv_m, fwd_m)
+    err = errors(inv, fwd)
     flops = 5.0 * n ** 3 * math.log2(n ** 3) * B
     alg = 8.0 * n ** 3 * B + 2.0 * n * n * B
     rec = _base_record(2 * flops / (ms * 1e-3) / 1e9, "GFLOP/s", args, ms,
@@ -804,23 +905,30 @@ def bench_q16(args, prec):
                        {"n": n, "batch": B, "precision": prec + "_scaled",
                         "input": "sphere-cutoff plane-wave coefficients, seeds 3000+j, quantized on the GPU"},
                        dtype="f32 arithmetic, %s storage" % prec)
-    dom = max(range(len(passes)), key=lambda k: passes[k])
+    f = 1 if prec == "fp16" else 2
+
+    def roof(per, mfma):
+        # the slower of the two transforms (launches 0-1 inverse, 2-3 forward)
+        t = max((0, 2), key=lambda i: per[i] + per[i + 1])
+        sg = "1" if t == 0 else "-1"
+        kern = ["k_q16_plane<128, %s, %d, %s" % (sg, f, "true" if mfma else "false"),
+                "k_q16_slab<128, %s, %d, %s" % (sg, f, "true" if mfma else "false")]
+        return transform_roofline(alg, per[t] + per[t + 1],
+                                  "%s transform: %s" % ("inverse" if t == 0 else "forward",
+                                                        " + ".join(k + ", ...>" for k in kern)),
+                                  traffic_sum(args.workload, kern), launches=2)
+
     rec.update({
         "hbm_gbs_algorithmic": round(2 * alg / (ms * 1e-3) / 1e9, 1),
         "hbm_frac_algorithmic": round(2 * alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "rel_l2_vs_fp64": {"inverse_vs_dequantized_input_max": max(e_inv), "forward_max": max(e_fwd),
-                           "inverse_vs_original_fp32_input_max": max(e_orig), "grids": [0, 16, 31]},
+        "rel_l2_vs_fp64": err,
         "fp32_same_step_ms": round(ms32, 5), "speedup_vs_fp32": round(ms32 / ms, 3),
         "radix16_engine_ms": {"valu_default": round(ms, 5), "mfma": round(ms_mfma, 5)},
-        "kernels_ms_inverse": [round(t, 5) for t in passes],
-        "plans": {"inverse": inv.describe()},
-        "roofline": {"bound": "hbm", "achieved": round(alg / (passes[dom] * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(alg / (passes[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     # a prefix: the plane kernel's name carries one more template argument
-                     "traffic": measured_traffic(args.workload, "%s<128, 1, %d, false" % (
-                         ["k_q16_plane", "k_q16_slab"][dom], 1 if prec == "fp16" else 2)),
-                     "kernel": ["k_q16_plane", "k_q16_slab"][dom] + "<128,1>",
-                     "ms_per_launch": round(passes[dom], 5)},
+        "mfma_engine": {"rel_l2_vs_fp64": err_m, "kernels_ms": [round(t, 5) for t in per_launch_m],
+                        "roofline": roof(per_launch_m, True)},
+        "kernels_ms": [round(t, 5) for t in per_launch],
+        "plans": {"inverse": inv.describe(), "inverse_mfma": inv_m.describe()},
+        "roofline": roof(per_launch, False),
         "cpu_baseline": None,
         "source_hash": source_hash(),
     })

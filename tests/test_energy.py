@@ -10,10 +10,10 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-# FP32 results are held to relative error 5e-6 against FP64.  E = sum V|psi|^2
-# with V of both signs partly cancels, so its relative error exceeds that of
-# psi (measured 1.4e-6 on the 128 x 96^3 orbital batch, psi ~1.5e-7).
-E_TOL = 5e-6
+# FP32 transforms and gradients are held to relative L2 error 5e-6 against
+# FP64; the scalar E = sum V|psi|^2 to relative error 1e-6 (its FP32 products
+# are summed in FP64; measured 1.9e-7 on the 128 x 96^3 orbital batch).
+E_TOL = 1e-6
 
 
 def rel(a, b):

@@ -136,17 +136,17 @@ def test_invariants_on_gpu_output(fft3d):
 
 
 def test_full_batch_128(fft3d):
-    """32 x 128^3 sphere-cutoff batch (the large FP32 workload): three grids
-    checked in full against the oracle, every grid checked by Parseval."""
+    """32 x 128^3 sphere-cutoff batch (the large FP32 workload): every grid
+    against the oracle element by element, and by Parseval."""
     B, n = 32, 128
     x = np.empty((B, n, n, n), np.complex64)
     for j in range(B):
         x[j] = workloads.sphere_grid(n, workloads.SEED_BATCH128 + j)
     for direction in (1, -1):
         got, _ = run(fft3d, x, direction)
-        for j in (0, 17, 31):
+        for j in range(B):
             ref = oracle.fft3d(x[j].astype(np.complex128), direction)
-            assert rel(got[j], ref) <= TOL, (direction, j)
+            assert rel(got[j], ref) <= TOL, (direction, j, rel(got[j], ref))
         ef = np.sum(np.abs(x.astype(np.complex128)) ** 2, axis=(1, 2, 3))
         eF = np.sum(np.abs(got.astype(np.complex128)) ** 2, axis=(1, 2, 3))
         assert np.all(np.abs(eF - n ** 3 * ef) <= 1e-5 * n ** 3 * ef)

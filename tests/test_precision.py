@@ -127,31 +127,61 @@ def test_matches_fp32_path(F):
     assert rel(oracle.q16_decode(pout, eout, oracle.FMT_FP16), y32) <= TOL16
 
 
-@pytest.mark.parametrize("prec", ["fp16", "bf16"])
-def test_batch_32x128(F, prec):
-    """32 grids of 128^3 (the large precision-form workload)."""
-    B, n = 32, 128
+def batch_128(B=32, n=128):
     x = np.empty((B, n, n, n), np.complex64)
     for j in range(B):
         x[j] = workloads.sphere_grid(n, workloads.SEED_BATCH128 + j)
+    return x
+
+
+def check_every_grid(pin, ein, pout, eout, prec, direction):
+    """Every grid of the batch against the FP64 oracle on its dequantized
+    input, element by element (relative L2 per grid)."""
+    worst = 0.0
+    for j in range(pin.shape[0]):
+        xin = oracle.q16_decode(pin[j:j + 1], ein[j:j + 1], FMT[prec])
+        got = oracle.q16_decode(pout[j:j + 1], eout[j:j + 1], FMT[prec])
+        r = rel(got, oracle.fft3d(xin, direction))
+        assert r <= TOL16, (prec, direction, j, r)
+        worst = max(worst, r)
+    return worst
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_batch_32x128(F, prec, monkeypatch):
+    """32 grids of 128^3 (the large precision-form workload) with the default
+    vector-ALU radix-16 engine, every grid, both directions."""
+    monkeypatch.delenv("FFT3D_Q16_MFMA", raising=False)
+    x = batch_128()
     for direction in (1, -1):
-        _, pin, ein, pout, eout = run_q16(F, x, prec, direction)
-        for j in (0, 17, 31):
-            xin = oracle.q16_decode(pin[j:j + 1], ein[j:j + 1], FMT[prec])
-            got = oracle.q16_decode(pout[j:j + 1], eout[j:j + 1], FMT[prec])
-            r = rel(got, oracle.fft3d(xin, direction))
-            assert r <= TOL16, (prec, direction, j, r)
+        plan, pin, ein, pout, eout = run_q16(F, x, prec, direction)
+        assert "radix-16 on VALU" in plan.describe()
+        check_every_grid(pin, ein, pout, eout, prec, direction)
 
 
 @pytest.mark.parametrize("n", [16, 64, 128])
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
-def test_mfma_engine_within_bound(F, n, prec, monkeypatch):
+@pytest.mark.parametrize("direction", [1, -1])
+def test_mfma_engine_within_bound(F, n, prec, direction, monkeypatch):
     """The same transform with the radix-16 stage as a DFT-matrix product on
-    the matrix cores (FFT3D_Q16_MFMA=1)."""
+    the matrix cores (FFT3D_Q16_MFMA=1), both signs of the DFT matrix."""
     monkeypatch.setenv("FFT3D_Q16_MFMA", "1")
     x = np.stack([workloads.sphere_grid(n, 300 + n + j) for j in range(2)])
-    plan, pin, ein, pout, eout = run_q16(F, x, prec, 1)
+    plan, pin, ein, pout, eout = run_q16(F, x, prec, direction)
     assert "radix-16 on MFMA" in plan.describe()
     xin = oracle.q16_decode(pin, ein, FMT[prec])
     got = oracle.q16_decode(pout, eout, FMT[prec])
-    assert rel(got, oracle.fft3d(xin, 1)) <= TOL16
+    assert rel(got, oracle.fft3d(xin, direction)) <= TOL16
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_mfma_batch_32x128(F, prec, monkeypatch):
+    """The matrix-core engine on the full 32 x 128^3 batch: these are the
+    launches with streaming loads that only a batch of 32 MB or more takes;
+    every grid, both directions."""
+    monkeypatch.setenv("FFT3D_Q16_MFMA", "1")
+    x = batch_128()
+    for direction in (1, -1):
+        plan, pin, ein, pout, eout = run_q16(F, x, prec, direction)
+        assert "radix-16 on MFMA" in plan.describe()
+        check_every_grid(pin, ein, pout, eout, prec, direction)
