@@ -81,7 +81,8 @@ enum fft3d_status {
     FFT3D_E_LAUNCH = -5,           /* a kernel launch or HIP call failed */
     FFT3D_E_ALIGNMENT = -6,        /* a data pointer is not 16-byte aligned */
     FFT3D_E_UNSUPPORTED = -7,      /* valid arguments, combination not provided */
-    FFT3D_E_TIMEOUT = -8           /* a bounded in-kernel wait expired (see fft3d_plan_check) */
+    FFT3D_E_TIMEOUT = -8,          /* a bounded in-kernel wait expired (see fft3d_plan_check) */
+    FFT3D_E_SCRATCH = -9           /* problem too large for the fixed scratch of fft3d_energy_noalloc */
 };
 
 /*
@@ -346,6 +347,36 @@ int fft3d_energy_fwd(fft3d_plan_t plan, const void *c, const float *V, void *psi
  */
 int fft3d_energy(fft3d_plan_t plan, const void *c, const float *V, void *work, double *E_dev,
                  fft3d_stream_t stream);
+
+/*
+ * fft3d_energy without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same E as fft3d_energy on a plan of `batch`
+ * orbitals of nx * ny * nz points (bit-identical: the same kernels, tables
+ * and summation order), without a plan.  The twiddle tables and the
+ * per-workgroup partial sums live in a fixed 1 MiB device array of the
+ * library, one per GPU it runs on, held until the process ends.  The call
+ * allocates nothing; it enqueues on `stream` a table fill, the xy-plane
+ * pass c -> work, the E-only z pass and the final sum into E_dev[0].
+ *   Limits: nx == ny; every dimension 2^a 3^b 5^c in 1..128; the partial
+ *   sums, ceil(batch*ny*nx / 64) doubles, must fit the array: batch*nx*ny
+ *   <= 8,355,840 (e.g. batch <= 510 at 128^2, <= 906 at 96^2); beyond it
+ *   FFT3D_E_SCRATCH.
+ *   Every call on one GPU uses that GPU's single array, which keeps the
+ *   last call's contents: calls that overlap on one GPU (two streams, two
+ *   host threads without ordering) race and give wrong results.  The first
+ *   call on a device looks the array up (hipGetSymbolAddress) and must not
+ *   itself be under stream capture; later calls may be captured.
+ * c, work: device complex64 [batch][nz][ny][nx] (work receives the
+ * xy-transformed orbitals, contents afterwards unspecified; work == c
+ * allowed and then overwrites c); V: device float [nz][ny][nx]; E_dev:
+ * device double.  Returns FFT3D_OK, FFT3D_E_INVALID_ARG (NULL pointer,
+ * size or batch < 1), FFT3D_E_ALIGNMENT (c, work, V not 16-byte, E_dev not
+ * 8-byte aligned), FFT3D_E_UNSUPPORTED_SIZE, FFT3D_E_UNSUPPORTED
+ * (nx != ny), FFT3D_E_SCRATCH, FFT3D_E_NO_DEVICE or FFT3D_E_LAUNCH.
+ */
+int fft3d_energy_noalloc(int nx, int ny, int nz, int batch, const void *c, const float *V, void *work,
+                         double *E_dev, fft3d_stream_t stream);
 
 /*
  * The local-potential operator itself, out_n = s * forward(V * inverse(c_n))

@@ -21,6 +21,7 @@ FFT3D_E_LAUNCH = -5
 FFT3D_E_ALIGNMENT = -6
 FFT3D_E_UNSUPPORTED = -7
 FFT3D_E_TIMEOUT = -8
+FFT3D_E_SCRATCH = -9
 
 FFT3D_FP32 = 0
 FFT3D_FP16_SCALED = 1
@@ -61,6 +62,7 @@ SIGNATURES = {
     "fft3d_energy": (_ci, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "fft3d_energy_bwd": (_ci, [_vp, _vp, _ci, _vp, _vp, _vp, _vp]),
     "fft3d_exec_pass": (_ci, [_vp, _ci, _vp, _vp, _vp]),
+    "fft3d_energy_noalloc": (_ci, [_ci, _ci, _ci, _ci, _vp, _vp, _vp, _vp, _vp]),
 }
 
 _lib = None

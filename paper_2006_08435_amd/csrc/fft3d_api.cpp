@@ -35,10 +35,11 @@ int set_error(int code)
 
 // Angles are reduced to an integer index modulo the root order before
 // cos/sin (double precision), then rounded once to float.
-std::vector<float2> twiddles(int n, int sign, int kind)
+int twiddles_into(float2* t, int cap, int n, int sign, int kind)
 {
     const Sched sc = make_sched_kind(n, kind);
-    std::vector<float2> t(sched_tw_len(sc) > 0 ? sched_tw_len(sc) : 0);
+    const int len = sched_tw_len(sc) > 0 ? sched_tw_len(sc) : 0;
+    if (len > cap) return -1;
     for (int s = 1; s < sc.count; ++s) {
         const int R = sc.r[s], NS = sched_ns(sc, s), order = NS * R;
         const int off = sched_tw_off(sc, s);
@@ -49,6 +50,14 @@ std::vector<float2> twiddles(int n, int sign, int kind)
                 t[off + k * (R - 1) + (q - 1)] = make_float2((float)std::cos(a), (float)(sign * std::sin(a)));
             }
     }
+    return len;
+}
+
+std::vector<float2> twiddles(int n, int sign, int kind)
+{
+    const Sched sc = make_sched_kind(n, kind);
+    std::vector<float2> t(sched_tw_len(sc) > 0 ? sched_tw_len(sc) : 0);
+    if (!t.empty()) twiddles_into(t.data(), (int)t.size(), n, sign, kind);
     return t;
 }
 
@@ -88,6 +97,7 @@ const char* fft3d_strerror(int code)
     case FFT3D_E_ALIGNMENT: return "data pointer not 16-byte aligned";
     case FFT3D_E_UNSUPPORTED: return "valid arguments, combination not provided";
     case FFT3D_E_TIMEOUT: return "a bounded in-kernel wait expired (result invalid)";
+    case FFT3D_E_SCRATCH: return "problem exceeds the fixed scratch array of the no-allocation entry point";
     default: return "unknown status";
     }
 }

@@ -19,6 +19,9 @@ void clear_error();
 bool env_flag(const char* name);
 // Twiddle table of a length-n transform for exponent sign `sign` (sched.hpp layout).
 std::vector<float2> twiddles(int n, int sign, int kind = 0);
+// The same table written to t[0 .. len) without allocating; returns len, or
+// -1 if it exceeds cap.
+int twiddles_into(float2* t, int cap, int n, int sign, int kind = 0);
 
 // One kernel launch of an exec.  The first pass reads the caller's input,
 // every later pass works in place on the output buffer.

@@ -79,6 +79,20 @@ def test_null_handles():
     assert lib.fft3d_apply_potential(None, None, None, None, None, None, None) == -1
     assert lib.fft3d_density(None, None, None, None, None, None) == -1
     assert lib.fft3d_energy(None, None, None, None, None, None) == -1
+    assert lib.fft3d_energy_noalloc(16, 16, 16, 1, None, None, None, None, None) == -1
+
+
+def test_noalloc_argument_checks():
+    """The no-allocation entry point checks its arguments before any HIP call
+    (the pointers below are never dereferenced)."""
+    lib = _lib().lib()
+    f = lib.fft3d_energy_noalloc
+    assert f(16, 16, 16, 0, 4096, 4096, 4096, 4096, None) == -1
+    assert f(16, 16, 16, 1, 4104, 4096, 4096, 4096, None) == -6
+    assert f(16, 16, 16, 1, 4096, 4096, 4096, 4100, None) == -6
+    assert f(14, 14, 16, 1, 4096, 4096, 4096, 4096, None) == -2
+    assert f(16, 8, 16, 1, 4096, 4096, 4096, 4096, None) == -7
+    assert f(128, 128, 1, 511, 4096, 4096, 4096, 4096, None) == -9
 
 
 def test_stream_copy_argument_checks():
@@ -94,11 +108,11 @@ def test_stream_copy_argument_checks():
 def test_strerror_covers_codes():
     lib = _lib().lib()
     seen = set()
-    for c in range(0, -9, -1):
+    for c in range(0, -10, -1):
         s = lib.fft3d_strerror(c).decode()
         assert s and s != "unknown status"
         seen.add(s)
-    assert len(seen) == 9
+    assert len(seen) == 10
     assert lib.fft3d_strerror(-99).decode() == "unknown status"
 
 
