@@ -481,20 +481,10 @@ int oracle_q16_decode(int fmt, long rows, int row_len, const uint16_t *payload,
 /* ------------------------------------------------------------------------ */
 
 /*
- * psi_n = unnormalised inverse transform of c_n (sign +1), for every orbital n
- * of the batch;  E = sum_n sum_r V(r) |psi_n(r)|^2 (V real, shared).
- * Gradient in the convention dE/dRe(c) + i dE/dIm(c) (what automatic
- * differentiation of a real function of complex inputs returns):
- *   grad_n = 2 * forward transform (sign -1) of V * psi_n,
- * because E is a Hermitian form in c and the adjoint of the unnormalised
- * inverse is the unnormalised forward transform.
- * psi and grad may be NULL.
- */
-/*
  * The local-potential operator of a plane-wave code applied to coefficient
  * grids c_n: out_n = forward transform (sign -1) of V * inverse transform
  * (sign +1) of c_n, both unnormalised (so a constant V = v gives
- * out = v * Nx*Ny*Nz * c).  This is half the gradient of the energy below.
+ * out = v * Nx*Ny*Nz * c).  This is half the gradient of oracle_energy's E.
  */
 int oracle_apply_potential(int nx, int ny, int nz, int batch, const double *c,
                            const double *V, double *out)
@@ -542,6 +532,16 @@ int oracle_density(int nx, int ny, int nz, int batch, const double *c,
     return err;
 }
 
+/*
+ * psi_n = unnormalised inverse transform of c_n (sign +1), for every orbital n
+ * of the batch;  E = sum_n sum_r V(r) |psi_n(r)|^2 (V real, shared).
+ * Gradient in the convention dE/dRe(c) + i dE/dIm(c) (what automatic
+ * differentiation of a real function of complex inputs returns):
+ *   grad_n = 2 * forward transform (sign -1) of V * psi_n,
+ * because E is a Hermitian form in c and the adjoint of the unnormalised
+ * inverse is the unnormalised forward transform.
+ * psi and grad may be NULL.
+ */
 int oracle_energy(int nx, int ny, int nz, int batch, const double *c,
                   const double *V, double *E, double *psi, double *grad)
 {
