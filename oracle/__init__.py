@@ -92,8 +92,13 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            build()
-            _lib = _bind(ctypes.CDLL(_LIB))
+            # FFT3D_ORACLE_LIB: another build of oracle.c (the sanitizer test
+            # runs the pins against an address/undefined-behaviour
+            # instrumented one)
+            alt = os.environ.get("FFT3D_ORACLE_LIB")
+            if not alt:
+                build()
+            _lib = _bind(ctypes.CDLL(alt or _LIB))
         return _lib
 
 

@@ -10,7 +10,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfft3d.so")
+# FFT3D_LIB_PATH: another build of the same sources (the sanitizer test loads
+# one whose host code is address/undefined-behaviour instrumented).
+LIB_PATH = os.environ.get("FFT3D_LIB_PATH") or os.path.join(_HERE, "libfft3d.so")
 
 FFT3D_OK = 0
 FFT3D_E_INVALID_ARG = -1
