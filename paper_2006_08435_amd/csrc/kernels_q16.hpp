@@ -301,6 +301,65 @@ __device__ __forceinline__ void q16_last_stage_store(const float2* lds, const fl
     }
 }
 
+// The slab pass's input held for its first z stage straight from registers:
+// thread (x = tid % N, j = tid / N) holds the 16 inputs z = j + q N/16
+// (q < 16) of its radix-16 butterfly of line x, one scaled16 word each
+// (lanes along x: every load instruction reads whole rows), and the row
+// exponents.  When N is a multiple of 64 a wave shares j, so lane q < 16
+// loads the exponent of z = j + q N/16 and the others are taken from it
+// with readlane; otherwise every thread loads its 16 exponents.  Slab rows
+// (b, z, y) lie N rows apart from row0 = (b, 0, y); offsets are 32-bit from
+// the slab's base (a slab spans < 2^32 elements).  Threads from N N/16 on
+// (T is rounded up to whole waves) hold nothing.
+template <int N, int T>
+struct Q16ColRegs {
+    static constexpr int M0 = N / 16, NB = N * M0;
+    static_assert(T >= NB && (N % 64 != 0 || T == NB), "one first-stage butterfly per thread");
+    static constexpr bool WAVE_J = N % 64 == 0;
+    unsigned u[16];
+    int e[WAVE_J ? 1 : 4];   // else the 16 exponents as bytes, four per word
+    __device__ __forceinline__ void load(const unsigned* pay, const signed char* ex, int tid)
+    {
+        if (NB < T && tid >= NB) return;
+        const int x = tid % N, j = tid / N;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) u[q] = pay[(unsigned)((j + M0 * q) * N * N + x)];
+        if constexpr (WAVE_J) {
+            const int lane = tid & 63;
+            e[0] = lane < 16 ? (int)ex[(unsigned)((j + M0 * lane) * N)] : 0;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) e[k] = 0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                e[q >> 2] |= ((int)(unsigned char)ex[(unsigned)((j + M0 * q) * N)]) << (8 * (q & 3));
+        }
+    }
+    template <int FMT>
+    __device__ __forceinline__ float2 value(int q) const
+    {
+        int eq;
+        if constexpr (WAVE_J) eq = __builtin_amdgcn_readlane(e[0], q);
+        else eq = (int)(signed char)(e[q >> 2] >> (8 * (q & 3)));
+        return make_float2(ldexpf(dec16<FMT>(u[q] & 0xFFFFu), eq), ldexpf(dec16<FMT>(u[q] >> 16), eq));
+    }
+    // Stage 0 of the KIND-1 schedule (radix 16, no twiddles) on the held
+    // values, written to the LDS tile (lines = x, element stride ES) in the
+    // stage's Stockham output order: element 16 j + q.
+    template <int S, int ES, int FMT>
+    __device__ __forceinline__ void stage0_to_lds(float2* lds, int tid) const
+    {
+        if (NB < T && tid >= NB) return;
+        const int x = tid % N, j = tid / N;
+        float2 v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = value<FMT>(q);
+        dft<16, S>(v);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) lds[x + (16 * j + q) * ES] = v[q];
+    }
+};
+
 // Pass A: planes p = b * N + z, persistent over `planes` with the next plane
 // prefetched into registers.  Rows of the input (b, z, y) -> rows of the FP16
 // intermediate (b, z, ky).  NT: streaming input loads.
@@ -356,6 +415,31 @@ k_q16_slab(const unsigned* mid_pay, const signed char* mid_exp, unsigned* out_pa
         return (s / N) * N * N + (s % N);
     };
     long s = blockIdx.x;
+    if constexpr (!MFMA && Plan1D<N, 1>::stages == 2) {
+        // First z stage straight from the loaded registers: one LDS write,
+        // one barrier, then the last stage (one LDS sweep and a barrier
+        // fewer per slab than staging the dequantized slab through LDS).
+        Q16ColRegs<N, T> cr;
+        if (s < slabs) cr.load(mid_pay + row0(s) * N, mid_exp + row0(s), tid);
+        for (; s < slabs; s += gridDim.x) {
+            cr.template stage0_to_lds<S, RS, kFmtF16>(lds, tid);
+            const long sn = s + gridDim.x;
+            if (sn < slabs) cr.load(mid_pay + row0(sn) * N, mid_exp + row0(sn), tid);
+            __syncthreads();
+            if constexpr (q16_wave_rows<N, T>()) {
+                q16_last_stage_store<N, S, T, RS, FMT_OUT>(lds, tw, out_pay + row0(s) * N, N * N, out_exp + row0(s),
+                                                           N, tid);
+            } else {
+                const LdsAcc<1, RS> a{lds};
+                fft_stage_p<Plan1D<N, 1>, 1, S, N, T, true, false>(a, a, tw, tid);
+                __syncthreads();
+                q16_store_rows<N, N, RS, T, FMT_OUT>(lds, out_pay + row0(s) * N, (long)N * N, out_exp + row0(s), N,
+                                                     tid);
+            }
+            __syncthreads();   // the tile is read before the next slab's stage 0 writes it
+        }
+        return;
+    }
     if (s < slabs) regs.template load<true>(mid_pay + row0(s) * N, (long)N * N, mid_exp + row0(s), N, tid);
     for (; s < slabs; s += gridDim.x) {
         regs.put_exponent(lds_e, tid);
