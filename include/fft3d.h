@@ -287,10 +287,12 @@ int fft3d_stream_copy(const void *src, void *dst, size_t bytes, fft3d_stream_t s
  * another persistent launch on a different stream.
  *
  * Returns NULL / FFT3D_E_UNSUPPORTED for non-cubic or unlisted sizes and
- * other precisions.  The schedule (threads per workgroup, items per queue
- * claim) is taken from the tuning cache ($FFT3D_TUNE_CACHE, default
+ * other precisions.  The schedule (launch mode, threads per workgroup, items
+ * per queue claim, and per group the radix order and z-tile width of its
+ * plain passes) is taken from the tuning cache ($FFT3D_TUNE_CACHE, default
  * ~/.cache/fft3d/tune.json), else tuned at plan time when FFT3D_TUNE=1,
- * else a default.
+ * else a default.  The results are valid only while fft3d_plan_check
+ * reports no expired wait (see there).
  */
 fft3d_plan_t fft3d_plan_many(int count, const int *nx, const int *ny, const int *nz, const int *batch,
                              int precision, int direction);
@@ -303,8 +305,17 @@ int fft3d_exec_many(fft3d_plan_t plan, const void *const *in, void *const *out, 
  * groups share one persistent launch with 512 / 1024 threads).  The tuner
  * times all of them. */
 int fft3d_plan_set_schedule(fft3d_plan_t plan, int threads, int chunk);
+/* Force the schedule of group `group`'s plain passes (grouped mode, and
+ * the big groups of the hybrid mode): radix_order 0 = the default radix
+ * order of its length, 1 = the alternative order (the default's two radices
+ * swapped, or the length split another way: 36 = 9x4, 64 = 16x4,
+ * 100 = 4x5x5); z_lines = 64 or 32 adjacent z-lines per workgroup of the z
+ * pass.  Returns FFT3D_OK or FFT3D_E_INVALID_ARG. */
+int fft3d_plan_set_group_schedule(fft3d_plan_t plan, int group, int radix_order, int z_lines);
 /* Time every schedule candidate on scratch buffers (synchronous), keep the
- * fastest and record it in the tuning cache. */
+ * fastest and record it in the tuning cache: first, per group, the radix
+ * order and z-tile width of its plain passes (that group alone); then the
+ * launch mode with its threads and chunk. */
 int fft3d_plan_tune(fft3d_plan_t plan);
 
 /*

@@ -205,6 +205,12 @@ class PlanMany:
     def set_schedule(self, threads: int, chunk: int) -> None:
         _lib.check(_lib.lib().fft3d_plan_set_schedule(self._h, int(threads), int(chunk)), "set_schedule")
 
+    def set_group_schedule(self, group: int, radix_order: int, z_lines: int) -> None:
+        """Radix order (0 default, 1 alternative) and z-tile width (32 or
+        64 lines) of group `group`'s plain passes."""
+        _lib.check(_lib.lib().fft3d_plan_set_group_schedule(self._h, int(group), int(radix_order), int(z_lines)),
+                   "set_group_schedule")
+
     def tune(self) -> None:
         _lib.check(_lib.lib().fft3d_plan_tune(self._h), "fft3d_plan_tune")
 

@@ -59,6 +59,7 @@ SIGNATURES = {
     "fft3d_plan_many": (_vp, [_ci, _vp, _vp, _vp, _vp, _ci, _ci]),
     "fft3d_exec_many": (_ci, [_vp, _vp, _vp, _vp]),
     "fft3d_plan_set_schedule": (_ci, [_vp, _ci, _ci]),
+    "fft3d_plan_set_group_schedule": (_ci, [_vp, _ci, _ci, _ci]),
     "fft3d_plan_tune": (_ci, [_vp]),
     "fft3d_energy_fwd": (_ci, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "fft3d_energy": (_ci, [_vp, _vp, _vp, _vp, _vp, _vp]),

@@ -108,9 +108,22 @@ __device__ __forceinline__ void store_coherent(float2* p, float2 v)
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Global memory, lines adjacent (line stride 1), runtime element stride;
-// COH_LOAD selects device-coherent loads.
-template <bool COH_LOAD = false>
+// 8-byte global load that misses the compute unit's L1 cache and is served
+// by the L2 of the XCD the workgroup runs on (sc0 on gfx950): it sees every
+// store that another compute unit of the same XCD has completed into that
+// L2 (the XCD's L2 is shared by its 32 compute units; only the L1 caches
+// are private).
+__device__ __forceinline__ float2 load_xcd_coherent(const float2* p)
+{
+    const unsigned long long b = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+    return __builtin_bit_cast(float2, b);
+}
+
+// Global memory, lines adjacent (line stride 1), runtime element stride.
+// COH_LOAD: 0 plain loads, 1 device-coherent loads (load_coherent), 2 loads
+// coherent within the XCD (load_xcd_coherent).
+template <int COH_LOAD = 0>
 struct GlobLines {
     const float2* src;
     float2* dst;
@@ -118,7 +131,8 @@ struct GlobLines {
     __device__ __forceinline__ float2 load(int line, int e) const
     {
         const float2* p = src + line + (long)e * es;
-        if constexpr (COH_LOAD) return load_coherent(p);
+        if constexpr (COH_LOAD == 1) return load_coherent(p);
+        else if constexpr (COH_LOAD == 2) return load_xcd_coherent(p);
         else return *p;
     }
     __device__ __forceinline__ void store(int line, int e, float2 v) const { dst[line + (long)e * es] = v; }
@@ -175,11 +189,12 @@ __device__ __forceinline__ void fft_stage_p(const Src& src, const Dst& dst, cons
     }
 }
 
-template <int N, int ST, int S, int L, int T, bool LINE_FAST, bool SYNC, class Src, class Dst>
+// K: schedule kind of the length-N transform (Plan1D).
+template <int N, int ST, int S, int L, int T, bool LINE_FAST, bool SYNC, int K = 0, class Src, class Dst>
 __device__ __forceinline__ void fft_stage(const Src& src, const Dst& dst, const float2* __restrict__ tw, int tid,
                                           int valid_lines = L)
 {
-    fft_stage_p<Plan1D<N>, ST, S, L, T, LINE_FAST, SYNC>(src, dst, tw, tid, valid_lines);
+    fft_stage_p<Plan1D<N, K>, ST, S, L, T, LINE_FAST, SYNC>(src, dst, tw, tid, valid_lines);
 }
 
 // All stages of a length-N transform on an LDS tile, in place.
@@ -187,21 +202,22 @@ __device__ __forceinline__ void fft_stage(const Src& src, const Dst& dst, const 
 // the last needs a barrier between its reads and its writes; in the last
 // stage each thread writes exactly the positions it read (j + q N/R), so it
 // needs none.
-template <int N, int S, int L, int T, int LS, int ES>
+template <int N, int S, int L, int T, int LS, int ES, int KIND = 0>
 __device__ __forceinline__ void fft_lds_all(float2* lds, const float2* __restrict__ tw, int tid,
                                             int valid_lines = L)
 {
-    using P = Plan1D<N>;
+    using P = Plan1D<N, KIND>;
     constexpr int K = P::stages;
+    constexpr int D = KIND;
     const LdsAcc<LS, ES> a{lds};
-    if constexpr (K > 0) { fft_stage<N, 0, S, L, T, true, (K > 1)>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (K > 1) { fft_stage<N, 1, S, L, T, true, (K > 2)>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (K > 2) { fft_stage<N, 2, S, L, T, true, (K > 3)>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (K > 3) { fft_stage<N, 3, S, L, T, true, (K > 4)>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (K > 4) { fft_stage<N, 4, S, L, T, true, (K > 5)>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (K > 5) { fft_stage<N, 5, S, L, T, true, (K > 6)>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (K > 6) { fft_stage<N, 6, S, L, T, true, (K > 7)>(a, a, tw, tid, valid_lines); __syncthreads(); }
-    if constexpr (K > 7) { fft_stage<N, 7, S, L, T, true, false>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 0) { fft_stage<N, 0, S, L, T, true, (K > 1), D>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 1) { fft_stage<N, 1, S, L, T, true, (K > 2), D>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 2) { fft_stage<N, 2, S, L, T, true, (K > 3), D>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 3) { fft_stage<N, 3, S, L, T, true, (K > 4), D>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 4) { fft_stage<N, 4, S, L, T, true, (K > 5), D>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 5) { fft_stage<N, 5, S, L, T, true, (K > 6), D>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 6) { fft_stage<N, 6, S, L, T, true, (K > 7), D>(a, a, tw, tid, valid_lines); __syncthreads(); }
+    if constexpr (K > 7) { fft_stage<N, 7, S, L, T, true, false, D>(a, a, tw, tid, valid_lines); __syncthreads(); }
 }
 
 }  // namespace fft3d

@@ -236,7 +236,16 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
         if (nxcc > 8) nxcc = 8;
         if (env_flag("FFT3D_LOG")) std::fprintf(stderr, "fft3d_plan: %d XCDs, %d resident workgroups\n", nxcc, resident);
         p->fused_xcd = fused_mode() == 2 ? nxcc : 0;
-        if (p->fused_xcd) p->fused_lag = (resident / nxcc + nx - 1) / nx + 1;
+        if (p->fused_xcd) {
+            // lag: the XCD's resident workgroups' worth of items, in grids
+            // (a lag of one grid, which would keep only two grids'
+            // intermediates in the XCD's L2, measured 1.8x slower at 64^3:
+            // the slab items wait).  FFT3D_FUSED_LAG overrides it.
+            const int res_x = fused_xcd_blocks_per_cu(nx) * cus;
+            p->fused_grid = (int)(items < res_x ? items : res_x);
+            const char* lg = std::getenv("FFT3D_FUSED_LAG");
+            p->fused_lag = lg && std::atoi(lg) > 0 ? std::atoi(lg) : (res_x / nxcc + nx - 1) / nx + 1;
+        }
         p->passes.push_back({Pass::kFusedK, nx, B, {}, p->tw_x});
     } else if (p->scheme == kCube) {
         p->passes.push_back({Pass::kCubeK, nx, B, {}, p->tw_x});

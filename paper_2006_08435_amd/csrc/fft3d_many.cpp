@@ -138,16 +138,28 @@ hipError_t launch_grouped(const fft3d_plan_s* p, const void* const* in, void* co
     hipError_t e = hipSuccess;
     for (int g = 0; g < mp.ngroups && e == hipSuccess; ++g) {
         if (only && !only[g]) continue;
-        const int n = mp.n[g];
+        const int n = mp.n[g], kind = mp.kind[g], zl = mp.zlines[g] ? mp.zlines[g] : kAxisLines;
         const long planes = (long)mp.batch[g] * n, resident = (long)plane_pf_blocks_per_cu(n) * cus;
-        const float2* tw = p->d_tw + mp.twoff_host[n];
+        const int grid = (int)(planes < resident ? planes : resident);
+        const float2* tw = p->d_tw + (kind == 2 ? mp.twoff_alt[n] : mp.twoff_host[n]);
         const float2* src = static_cast<const float2*>(in[g]);
         float2* dst = static_cast<float2*>(out[g]);
-        e = plane_pf_fn(n, p->direction)(src, dst, tw, planes, (int)(planes < resident ? planes : resident), 0,
-                                         nullptr, nullptr, n, true, st);
+        if (kind == 0) {
+            e = plane_pf_fn(n, p->direction)(src, dst, tw, planes, grid, 0, nullptr, nullptr, n, true, st);
+        } else {
+            const PlaneVarFn f = plane_variant_fn(n, p->direction, kind);
+            e = f ? f(src, dst, tw, planes, grid, true, st) : hipErrorInvalidValue;
+        }
         const long vol = (long)n * n * n;
         const AxisMap zmap{(long)mp.batch[g] * n * n, n, n, vol, (long)n, (long)n * n};
-        if (e == hipSuccess && n > 1) e = axis_str_fn(n, p->direction)(dst, dst, tw, zmap, 0, nullptr, nullptr, 0, st);
+        if (e == hipSuccess && n > 1) {
+            if (kind == 0 && zl == kAxisLines) {
+                e = axis_str_fn(n, p->direction)(dst, dst, tw, zmap, 0, nullptr, nullptr, 0, st);
+            } else {
+                const AxisVarFn f = axis_variant_fn(n, p->direction, kind, zl);
+                e = f ? f(dst, dst, tw, zmap, st) : hipErrorInvalidValue;
+            }
+        }
     }
     return e;
 }
@@ -194,8 +206,11 @@ std::string cache_key(const fft3d_plan_s* p)
     return k.str();
 }
 
-// The cache file holds one entry per line:  "key": {"threads": T, "chunk": K, "ms": t},
-// Lines that do not parse are ignored (a corrupt file means "no entries").
+// The cache file holds one entry per line:
+//   "key": {"threads": T, "chunk": K, "ms": t, "radix": "k0,k1,...", "zlines": "l0,l1,..."},
+// with one radix order (0 default, 2 alternative) and z-tile width per group.
+// Lines that do not parse are ignored (a corrupt file means "no entries");
+// an entry without the per-group fields selects the default variants.
 std::map<std::string, std::string> cache_read()
 {
     std::map<std::string, std::string> m;
@@ -211,26 +226,63 @@ std::map<std::string, std::string> cache_read()
     return m;
 }
 
-bool cache_lookup(const std::string& key, int& threads, int& chunk)
+// Per-group list "a,b,c" of `count` integers each in `ok`; false otherwise.
+bool parse_list(const std::string& v, const char* field, int count, int* out, bool (*ok)(int))
+{
+    const std::string tag = std::string("\"") + field + "\": \"";
+    const size_t a = v.find(tag);
+    if (a == std::string::npos) return false;
+    const size_t b = v.find('"', a + tag.size());
+    if (b == std::string::npos) return false;
+    std::stringstream ss(v.substr(a + tag.size(), b - a - tag.size()));
+    std::string item;
+    int k = 0;
+    while (std::getline(ss, item, ',')) {
+        char* end = nullptr;
+        const long x = std::strtol(item.c_str(), &end, 10);
+        if (k >= count || end == item.c_str() || *end != 0 || !ok((int)x)) return false;
+        out[k++] = (int)x;
+    }
+    return k == count;
+}
+
+bool kind_ok(int k) { return k == 0 || k == 2; }
+bool lines_ok(int l) { return l == 32 || l == 64; }
+
+bool cache_lookup(const std::string& key, int ngroups, int& threads, int& chunk, int* kind, int* zlines)
 {
     const auto m = cache_read();
     const auto it = m.find(key);
     if (it == m.end()) return false;
     int t = 0, c = 0;
     double ms = 0;
-    if (std::sscanf(it->second.c_str(), "{\"threads\": %d, \"chunk\": %d, \"ms\": %lf}", &t, &c, &ms) != 3) return false;
+    if (std::sscanf(it->second.c_str(), "{\"threads\": %d, \"chunk\": %d, \"ms\": %lf", &t, &c, &ms) != 3) return false;
     if ((t != 0 && t != 512 && t != 1024 && t != -512 && t != -1024) || c < 1 || c > 64) return false;
+    int k[kMaxGroups], l[kMaxGroups];
+    if (parse_list(it->second, "radix", ngroups, k, kind_ok) && parse_list(it->second, "zlines", ngroups, l, lines_ok)) {
+        for (int g = 0; g < ngroups; ++g) {
+            kind[g] = k[g];
+            zlines[g] = l[g];
+        }
+    }
     threads = t;
     chunk = c;
     return true;
 }
 
-void cache_store(const std::string& key, int threads, int chunk, double ms)
+void cache_store(const std::string& key, const ManyPlan& mp, double ms)
 {
     auto m = cache_read();
-    char v[128];
-    std::snprintf(v, sizeof v, "{\"threads\": %d, \"chunk\": %d, \"ms\": %.5f}", threads, chunk, ms);
-    m[key] = v;
+    std::ostringstream v;
+    char head[128];
+    std::snprintf(head, sizeof head, "{\"threads\": %d, \"chunk\": %d, \"ms\": %.5f, \"radix\": \"",
+                  mp.hybrid ? -mp.threads : mp.threads, mp.chunk, ms);
+    v << head;
+    for (int g = 0; g < mp.ngroups; ++g) v << (g ? "," : "") << mp.kind[g];
+    v << "\", \"zlines\": \"";
+    for (int g = 0; g < mp.ngroups; ++g) v << (g ? "," : "") << (mp.zlines[g] ? mp.zlines[g] : kAxisLines);
+    v << "\"}";
+    m[key] = v.str();
     const std::string path = cache_path();
     const size_t slash = path.rfind('/');
     if (slash != std::string::npos) {
@@ -263,10 +315,48 @@ int tune(fft3d_plan_s* p)
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (rc == FFT3D_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = FFT3D_E_LAUNCH;
+    auto time_runs = [&](const bool* only, float& ms_out) {
+        const void* const* ib = (const void* const*)bufs.data();
+        void* const* ob = bufs.data();
+        bool ok = true;
+        for (int w = 0; w < 2 && ok; ++w)
+            ok = (only ? launch_grouped(p, ib, ob, nullptr, only) : run_many(p, ib, ob, nullptr)) == hipSuccess;
+        ok = ok && hipEventRecord(e0, nullptr) == hipSuccess;
+        for (int r = 0; r < 5 && ok; ++r)
+            ok = (only ? launch_grouped(p, ib, ob, nullptr, only) : run_many(p, ib, ob, nullptr)) == hipSuccess;
+        ok = ok && hipEventRecord(e1, nullptr) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.f;
+        ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (!ok) (void)hipGetLastError();
+        ms_out = ms / 5;
+        return ok;
+    };
+    // 1. per group: the radix order and z-tile width of its plain passes,
+    //    timed on that group alone
+    const int cand_k[] = {0, 2}, cand_l[] = {kAxisLines, 32};
+    for (int g = 0; g < mp.ngroups && rc == FFT3D_OK; ++g) {
+        bool only[kMaxGroups] = {};
+        only[g] = true;
+        double gbest = 1e30;
+        int bk = 0, bl = kAxisLines;
+        for (int k : cand_k)
+            for (int l : cand_l) {
+                mp.kind[g] = k;
+                mp.zlines[g] = l;
+                float ms = 0.f;
+                if (time_runs(only, ms) && ms < gbest) {
+                    gbest = ms;
+                    bk = k;
+                    bl = l;
+                }
+            }
+        mp.kind[g] = bk;
+        mp.zlines[g] = bl;
+    }
+    // 2. the launch mode: the grouped mode, then the persistent kernel's and
+    //    the hybrid mode's (threads, chunk)
     double best = 1e30;
     int bt = mp.threads, bc = mp.chunk;
-    // candidates: the grouped mode, then the persistent kernel's and the
-    // hybrid mode's (threads, chunk)
     const int cand_t[] = {0, 1024, 512, -1024, -512};
     const int cand_c[] = {1, 2, 4, 8};
     for (int t : cand_t)
@@ -274,20 +364,12 @@ int tune(fft3d_plan_s* p)
             if (rc != FFT3D_OK) break;
             if (t == 0 && c != 1) continue;
             if (apply_schedule(p, t, c) != FFT3D_OK) continue;
-            const void* const* ib = (const void* const*)bufs.data();
-            void* const* ob = bufs.data();
-            bool ok = true;
-            for (int w = 0; w < 2 && ok; ++w) ok = run_many(p, ib, ob, nullptr) == hipSuccess;
-            ok = ok && hipEventRecord(e0, nullptr) == hipSuccess;
-            for (int r = 0; r < 5 && ok; ++r) ok = run_many(p, ib, ob, nullptr) == hipSuccess;
-            ok = ok && hipEventRecord(e1, nullptr) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
             float ms = 0.f;
-            if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms / 5 < best) {
-                best = ms / 5;
+            if (time_runs(nullptr, ms) && ms < best) {
+                best = ms;
                 bt = t;
                 bc = c;
             }
-            if (!ok) (void)hipGetLastError();
         }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -298,7 +380,7 @@ int tune(fft3d_plan_s* p)
     if (rc == FFT3D_OK) {
         mp.tuned = true;
         mp.tuned_ms = best;
-        cache_store(cache_key(p), bt, bc, best);
+        cache_store(cache_key(p), mp, best);
     }
     return rc;
 }
@@ -382,6 +464,11 @@ fft3d_plan_t fft3d_plan_many(int count, const int* nx, const int* ny, const int*
             const std::vector<float2> t = twiddles(nx[g], direction);
             tab.insert(tab.end(), t.begin(), t.end());
             if (tab.size() % 2) tab.push_back(make_float2(0.f, 0.f));
+            // the alternative radix order's table (tuner candidate)
+            mp.twoff_alt[nx[g]] = (int)tab.size();
+            const std::vector<float2> ta = twiddles(nx[g], direction, 2);
+            tab.insert(tab.end(), ta.begin(), ta.end());
+            if (tab.size() % 2) tab.push_back(make_float2(0.f, 0.f));
         }
     }
     if (tab.empty()) tab.push_back(make_float2(0.f, 0.f));
@@ -406,7 +493,8 @@ fft3d_plan_t fft3d_plan_many(int count, const int* nx, const int* ny, const int*
         return nullptr;
     }
     int threads = 1024, chunk = 2;
-    const bool cached = cache_lookup(cache_key(p), threads, chunk);
+    for (int g = 0; g < count; ++g) mp.zlines[g] = kAxisLines;
+    const bool cached = cache_lookup(cache_key(p), count, threads, chunk, mp.kind, mp.zlines);
     int rc = apply_schedule(p, threads, chunk);
     if (rc == FFT3D_OK && !cached && env_flag("FFT3D_TUNE")) rc = tune(p);
     if (rc != FFT3D_OK) {
@@ -443,6 +531,17 @@ int fft3d_plan_set_schedule(fft3d_plan_t p, int threads, int chunk)
     return rc;
 }
 
+int fft3d_plan_set_group_schedule(fft3d_plan_t p, int group, int radix_order, int z_lines)
+{
+    if (!p || !p->many || group < 0 || group >= p->mp.ngroups || (radix_order != 0 && radix_order != 1) ||
+        (z_lines != 32 && z_lines != 64))
+        return FFT3D_E_INVALID_ARG;
+    p->mp.kind[group] = radix_order ? 2 : 0;
+    p->mp.zlines[group] = z_lines;
+    p->mp.tuned = false;
+    return FFT3D_OK;
+}
+
 int fft3d_plan_tune(fft3d_plan_t p)
 {
     if (!p || !p->many) return FFT3D_E_INVALID_ARG;
@@ -477,6 +576,16 @@ int many_describe(fft3d_plan_t p, char* buf, size_t len)
         d << " mode=persistent threads=" << p->mp.threads << " chunk=" << p->mp.chunk << " workgroups=" << p->mp.grid
           << " lds=" << p->mp.lds << " items=" << p->mp.nitems << (p->mp.tuned ? " tuned" : " default")
           << (p->direction < 0 ? " forward" : " inverse") << " kernels=k_many";
+    }
+    if (p->mp.threads == 0 || p->mp.hybrid) {
+        d << " radix=";
+        for (int g = 0; g < p->mp.ngroups; ++g) {
+            const Sched sc = make_sched_kind(p->mp.n[g], p->mp.kind[g]);
+            d << (g ? "," : "");
+            for (int i = 0; i < sc.count; ++i) d << (i ? "x" : "") << sc.r[i];
+        }
+        d << " zlines=";
+        for (int g = 0; g < p->mp.ngroups; ++g) d << (g ? "," : "") << (p->mp.zlines[g] ? p->mp.zlines[g] : kAxisLines);
     }
     const std::string s = d.str();
     if (buf && len) {

@@ -34,6 +34,30 @@ static hipError_t launch_fused_xcd(const float2* in, float2* out, const float2* 
     return hipGetLastError();
 }
 
+template <int N>
+static int occupancy_xcd()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_fused_xcd<N, -1>),
+                                                     PlaneGeom<N>::T, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return nb > 0 ? nb : 1;
+}
+
+#define FFT3D_FUSED_XCD_OCC(n)                                                 \
+    case n:                                                                    \
+        return occupancy_xcd<n>();
+
+int fused_xcd_blocks_per_cu(int n)
+{
+    switch (n) {
+        FFT3D_FOR_EACH_FUSED_SIZE(FFT3D_FUSED_XCD_OCC)
+    default: return 1;
+    }
+}
+
 #define FFT3D_FUSED_XCD_CASE(n)                                                \
     case n:                                                                    \
         return sign < 0 ? &launch_fused_xcd<n, -1> : &launch_fused_xcd<n, 1>;

@@ -59,18 +59,19 @@ struct LdsAcc2 {
 // aliases `a` with another layout, so the last stage also needs a barrier
 // between its reads and its writes.  With last == a it needs none: the last
 // stage of a Stockham schedule writes exactly the positions it read.
-template <int N, int S, int L, int T, int ST, bool LAST_SYNC, class A, class D>
+// K: schedule kind (Plan1D).
+template <int N, int S, int L, int T, int ST, bool LAST_SYNC, int K = 0, class A, class D>
 __device__ __forceinline__ void run_tail(const A& a, const D& last, const float2* __restrict__ tw, int tid,
                                          int valid = L)
 {
-    using P = Plan1D<N>;
+    using P = Plan1D<N, K>;
     if constexpr (ST < P::stages) {
         if constexpr (ST == P::stages - 1) {
-            fft_stage<N, ST, S, L, T, true, LAST_SYNC>(a, last, tw, tid, valid);
+            fft_stage<N, ST, S, L, T, true, LAST_SYNC, K>(a, last, tw, tid, valid);
         } else {
-            fft_stage<N, ST, S, L, T, true, true>(a, a, tw, tid, valid);
+            fft_stage<N, ST, S, L, T, true, true, K>(a, a, tw, tid, valid);
             __syncthreads();
-            run_tail<N, S, L, T, ST + 1, LAST_SYNC>(a, last, tw, tid, valid);
+            run_tail<N, S, L, T, ST + 1, LAST_SYNC, K>(a, last, tw, tid, valid);
         }
     }
 }
@@ -360,7 +361,9 @@ k_plane(const float2* in, float2* out, const float2* __restrict__ tw)
 // prologue of the energy gradient.
 // NT: streaming plane loads (see stream_plane); the stores keep the default
 // policy so that the z pass after it finds their last part in the caches.
-template <int N, int S, bool SCALE = false, bool NT = false>
+// K: schedule kind of both 1D transforms (0 default, 2 the tuner's
+// alternative order; the twiddle table must be of the same kind).
+template <int N, int S, bool SCALE = false, bool NT = false, int K = 0>
 __global__ void __launch_bounds__(PlaneGeom<N>::T)
 k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long planes, const float* __restrict__ V,
            const double* __restrict__ gE, int nz)
@@ -386,10 +389,10 @@ k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long pl
             regs.load(in + pn * N * N, tid);
             if constexpr (SCALE) regs.load_factors(vr, V + (pn % nz) * N * N, tid);
         }
-        fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
+        fft_lds_all<N, S, N, T, RS, 1, K>(lds, tw, tid);
         const LdsAcc<1, RS> col{lds};
         const PlaneColOut<N> dst{out + p * N * N};
-        run_tail<N, S, N, T, 0, false>(col, dst, tw, tid);
+        run_tail<N, S, N, T, 0, false, K>(col, dst, tw, tid);
         __syncthreads();
     }
 }
@@ -573,8 +576,9 @@ k_sphere_copy(const float2* __restrict__ src, float2* __restrict__ dst, const Sp
 
 // One xz-slab for fixed (b, y): N lines (all x) of N points along z, element
 // z of line x at base[z * es + x].  Loads and stores run with lanes along x.
-// COH: the slab's input is loaded device-coherently.
-template <int N, int S, int T, bool COH = false>
+// COH: how the slab's input is loaded (GlobLines: 0 plain, 1 device-coherent,
+// 2 coherent within the XCD).
+template <int N, int S, int T, int COH = 0>
 __device__ __forceinline__ void slab_body(const float2* in, float2* out, long es, const float2* __restrict__ tw,
                                           float2* lds, int tid)
 {
@@ -718,13 +722,27 @@ k_fused(const float2* in, float2* out, const float2* __restrict__ tw, FusedCtl* 
 }
 
 // XCD-local form of the fused kernel.  Each XCD (accelerator complex die,
-// with its own L2) owns the grids g with g mod Q == its XCC id mod Q and has
-// its own item queue, so a grid's planes and slabs are transformed by
-// workgroups that share one L2: the intermediate is stored and loaded with
-// ordinary cached accesses, and a plane item is published once its stores
-// have completed into that L2.  The last workgroup to leave checks that every
-// queue was fully claimed (an XCD without workgroups would leave its grids
-// untransformed; that is reported through the timeout counter).
+// with its own L2 shared by its 32 compute units) owns the grids g with
+// g mod Q == its XCC id mod Q and has its own item queue, so a grid's planes
+// and slabs are transformed by workgroups that share one L2.  With a lag of
+// one grid at most two grids' intermediates are live per XCD (2 x 2 MiB at
+// 64^3, the size of the L2), so the intermediate is handed over through the
+// L2 instead of through HBM:
+//   * plane items store with ordinary stores (the L1 writes through to the
+//     L2); a plane item is published (its grid's counter incremented) after
+//     every wave has waited for all its memory operations, i.e. after its
+//     stores have completed into the L2;
+//   * slab items read the intermediate with loads that miss the L1 and are
+//     served by the L2 (load_xcd_coherent), issued after they have observed
+//     the counter, so no stale L1 line (e.g. of an in-place input) is used.
+// Workgroups claim one item ahead: while an item is transformed, the input
+// plane of the next item (when it is a plane item) is already loading into
+// registers (streaming loads: each input plane is read once).  Items are
+// still claimed in list order, so the earliest unfinished item is always
+// held by a running workgroup as its current item and progresses.  The last
+// workgroup to leave checks that every queue was fully claimed (an XCD
+// without workgroups would leave its grids untransformed; that is reported
+// through the timeout counter).
 struct XcdCtl {
     unsigned head[8][32];   // one queue counter per XCD, 128 bytes apart
     unsigned exited;
@@ -742,7 +760,7 @@ template <int N, int S>
 __global__ void __launch_bounds__(PlaneGeom<N>::T)
 k_fused_xcd(const float2* in, float2* out, const float2* __restrict__ tw, XcdCtl* ctl, int batch, int q, int lag)
 {
-    constexpr int T = PlaneGeom<N>::T;
+    constexpr int T = PlaneGeom<N>::T, RS = PlaneGeom<N>::RS;
     constexpr long V = (long)N * N * N;
     __shared__ float2 lds[PlaneGeom<N>::WORDS];
     __shared__ int item_sh;
@@ -751,6 +769,7 @@ k_fused_xcd(const float2* in, float2* out, const float2* __restrict__ tw, XcdCtl
     const int bq = (batch - x + q - 1) / q;     // grids of this XCD's queue
     const long total = 2L * bq * N;
     int pending = -1;
+    TileRegs<N, N, T, true> regs;
     auto publish = [&]() {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -758,18 +777,31 @@ k_fused_xcd(const float2* in, float2* out, const float2* __restrict__ tw, XcdCtl
             __hip_atomic_fetch_add(&ctl->done[pending], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         pending = -1;
     };
-    for (;;) {
+    auto claim = [&]() -> long {
         if (tid == 0) item_sh = (int)atomicAdd(&ctl->head[x][0], 1u);
         __syncthreads();
         const long it = item_sh;
-        if (it >= total) break;
-        const Item w = decode_item(it, N, bq, lag);
+        __syncthreads();
+        return it;
+    };
+    // input plane of item `it` into registers, if it is a plane item
+    auto prefetch = [&](long it) {
+        if (it < total) {
+            const Item w = decode_item(it, N, bq, lag);
+            if (!w.slab) regs.load(in + (w.g * q + x) * V + (long)w.idx * N * N, tid);
+        }
+    };
+    long cur = claim();
+    prefetch(cur);
+    while (cur < total) {
+        const Item w = decode_item(cur, N, bq, lag);
         const int g = w.g * q + x;
+        const long nxt = claim();
         if (!w.slab) {
             const long base = g * V + (long)w.idx * N * N;
-            constexpr int RS = PlaneGeom<N>::RS;
-            tile_to_lds<N, N, RS, T>(in + base, lds, tid);
-            publish();
+            regs.template store_lds<RS>(lds, tid);
+            publish();   // the previous plane's stores are complete by now
+            prefetch(nxt);
             fft_lds_all<N, S, N, T, RS, 1>(lds, tw, tid);
             const LdsAcc<1, RS> col{lds};
             const PlaneColOut<N, false> dst{out + base};
@@ -777,6 +809,7 @@ k_fused_xcd(const float2* in, float2* out, const float2* __restrict__ tw, XcdCtl
             pending = g;
         } else {
             publish();
+            prefetch(nxt);
             if (tid == 0) {
                 unsigned n = 0;
                 while (__hip_atomic_load(&ctl->done[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)N) {
@@ -789,9 +822,10 @@ k_fused_xcd(const float2* in, float2* out, const float2* __restrict__ tw, XcdCtl
             }
             __syncthreads();
             const long base = g * V + (long)w.idx * N;
-            slab_body<N, S, T, false>(out + base, out + base, (long)N * N, tw, lds, tid);
+            slab_body<N, S, T, 2>(out + base, out + base, (long)N * N, tw, lds, tid);
         }
-        __syncthreads();
+        __syncthreads();   // LDS reuse
+        cur = nxt;
     }
     publish();
     if (tid == 0) {
@@ -799,7 +833,8 @@ k_fused_xcd(const float2* in, float2* out, const float2* __restrict__ tw, XcdCtl
         if (prev == gridDim.x - 1) {
             for (int y = 0; y < q; ++y) {
                 const int by = (batch - y + q - 1) / q;
-                if (ctl->head[y][0] < (unsigned)(2L * by * N)) atomicAdd(&ctl->timeouts, 1u);   // queue not drained
+                // queue not drained (each workgroup claims once past the end)
+                if (ctl->head[y][0] < (unsigned)(2L * by * N)) atomicAdd(&ctl->timeouts, 1u);
                 ctl->head[y][0] = 0;
             }
             for (int gg = 0; gg < batch; ++gg) ctl->done[gg] = 0;
@@ -935,14 +970,17 @@ __device__ __forceinline__ long rev_tile() { return (long)(gridDim.x - 1 - block
 // forward (GlobStridedPruned), 3 z pass of the pruned forward into a packed
 // sphere (GlobZPacked: `out` is the packed buffer, npts points per grid).
 // 1 to 3 require the z-pass AxisMap.
-template <int N, int S, int L, bool ENERGY = false, int PRUNE = 0>
+// K: schedule kind (dense form only: 0 default, 2 the tuner's alternative
+// order, with a twiddle table of the same kind).
+template <int N, int S, int L, bool ENERGY = false, int PRUNE = 0, int K = 0>
 __global__ void __launch_bounds__((AxisGeom<N, L>::T))
 k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap m, const float* __restrict__ V,
            double* __restrict__ partials, long vol, double R2 = 0.0, const SphereRow* __restrict__ rows = nullptr,
            long npts = 0)
 {
+    static_assert(K == 0 || (!ENERGY && PRUNE == 0), "schedule kinds other than 0 serve the dense form only");
     using G = AxisGeom<N, L>;
-    using P = Plan1D<N>;
+    using P = Plan1D<N, K>;
     constexpr int T = G::T;
     static_assert(T % L == 0, "each thread keeps one line");
     __shared__ float2 lds[P::stages > 1 ? G::WORDS : 1];
@@ -1006,12 +1044,12 @@ k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap
         }
     } else {
         if constexpr (P::stages == 1) {
-            fft_stage<N, 0, S, L, T, true, false>(g, g, tw, tid, valid);
+            fft_stage<N, 0, S, L, T, true, false, K>(g, g, tw, tid, valid);
         } else {
             const LdsAcc<1, G::LP> a{lds};
-            fft_stage<N, 0, S, L, T, true, false>(g, a, tw, tid, valid);
+            fft_stage<N, 0, S, L, T, true, false, K>(g, a, tw, tid, valid);
             __syncthreads();
-            run_tail<N, S, L, T, 1, false>(a, g, tw, tid, valid);
+            run_tail<N, S, L, T, 1, false, K>(a, g, tw, tid, valid);
         }
     }
 }

@@ -53,6 +53,12 @@ struct ManyPlan {
     bool hybrid = false;
     bool big[kMaxGroups] = {};
     int twoff_host[129] = {};   // offset of the length-n table in the plan's twiddles
+    int twoff_alt[129] = {};    // offset of the length-n table of the alternative radix order
+    // per group, for its plain passes (grouped mode, and the big groups of
+    // the hybrid mode): radix order (0 default, 2 alternative) and z-tile
+    // lines (64 or 32); chosen by the tuner or fft3d_plan_set_group_schedule
+    int kind[kMaxGroups] = {};
+    int zlines[kMaxGroups] = {};
     int grid = 1;
     size_t lds = 0;
     bool tuned = false;

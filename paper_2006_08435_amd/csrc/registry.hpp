@@ -80,8 +80,22 @@ FusedFn fused_fn(int n, int sign);
 using FusedXcdFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, FusedCtl* ctl, int batch, int lag,
                                   int grid, int q, hipStream_t st);
 FusedXcdFn fused_xcd_fn(int n, int sign);
-// Workgroups of the fused kernel that fit on one compute unit at once.
+// Workgroups of the fused kernel (and of its XCD-local form) that fit on
+// one compute unit at once.
 int fused_blocks_per_cu(int n);
+int fused_xcd_blocks_per_cu(int n);
+
+// Schedule variants of the dense passes for the batched form's autotuner
+// (k_variants.hip), sizes of FFT3D_FOR_EACH_MANY_SIZE: kind 2 = the
+// alternative radix order (make_sched_alt; its twiddle table is
+// twiddles(n, sign, 2)), z tiles of `lines` = 32 or 64 lines.  nullptr for
+// combinations that are not compiled (kind 0 with 64 lines is the default
+// pair, plane_pf_fn / axis_str_fn).
+using PlaneVarFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, long planes, int grid, bool stream,
+                                  hipStream_t st);
+using AxisVarFn = hipError_t (*)(const float2* in, float2* out, const float2* tw, const AxisMap& m, hipStream_t st);
+PlaneVarFn plane_variant_fn(int n, int sign, int kind);
+AxisVarFn axis_variant_fn(int n, int sign, int kind, int lines);
 
 // Heterogeneous persistent kernel (kernels_many.hpp); threads is 512 or 1024.
 hipError_t launch_many(const ManyArgs& a, int sign, int threads, int grid, size_t lds_bytes, hipStream_t st);

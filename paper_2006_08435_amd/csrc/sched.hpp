@@ -133,9 +133,32 @@ __host__ __device__ constexpr Sched make_sched16(int n)
     return s;
 }
 
+// The autotuner's alternative schedule of n (kind 2): the default's two
+// radices in the other order, or, where the default repeats one radix, the
+// length split another way; lengths with neither keep the default.
+__host__ __device__ constexpr Sched make_sched_alt(int n)
+{
+    Sched s = make_sched(n);
+    if (s.count == 2 && s.r[0] != s.r[1]) {
+        const int t = s.r[0];
+        s.r[0] = s.r[1];
+        s.r[1] = t;
+        return s;
+    }
+    switch (n) {
+    case 16: return Sched{2, {4, 4, 0, 0, 0, 0, 0, 0}};
+    case 36: return Sched{2, {9, 4, 0, 0, 0, 0, 0, 0}};
+    case 64: return Sched{2, {16, 4, 0, 0, 0, 0, 0, 0}};
+    case 100: return Sched{3, {4, 5, 5, 0, 0, 0, 0, 0}};
+    default: return s;
+    }
+}
+
+// kind 0: default; 1: radix 16 first (reduced-precision form); 2: the
+// autotuner's alternative order.
 __host__ __device__ constexpr Sched make_sched_kind(int n, int kind)
 {
-    return kind == 1 ? make_sched16(n) : make_sched(n);
+    return kind == 1 ? make_sched16(n) : (kind == 2 ? make_sched_alt(n) : make_sched(n));
 }
 
 __host__ __device__ constexpr int sched_ns(const Sched& s, int stage)

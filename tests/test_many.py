@@ -187,6 +187,35 @@ def test_graph_capture_replays_match_eager(F, threads, chunk, groups):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("direction", [-1, 1])
+def test_group_schedule_variants_match_oracle(F, direction):
+    """Every radix order and z-tile width of the plain passes (the tuner's
+    candidates) against the oracle, on sizes whose alternative order swaps
+    two radices (48, 120) or splits the length another way (36 = 9x4,
+    64 = 16x4, 100 = 4x5x5: three stages)."""
+    groups = [(48, 2), (120, 1), (36, 2), (64, 2), (100, 1)]
+    xs = inputs(groups, 77)
+    refs = [[oracle.fft3d(x[j].astype(np.complex128), direction) for j in range(b)]
+            for (n, b), x in zip(groups, xs)]
+    plan = F.PlanMany(groups, direction)
+    plan.set_schedule(0, 1)   # grouped mode: every group runs its plain passes
+    radices = {0: "16x3,8x15,6x6,8x8,10x10", 1: "3x16,15x8,9x4,16x4,4x5x5"}
+    for order, lines in [(1, 64), (0, 32), (1, 32), (0, 64)]:
+        for g in range(len(groups)):
+            plan.set_group_schedule(g, order, lines)
+        d = plan.describe()
+        assert "radix=" + radices[order] in d and "zlines=" + ",".join([str(lines)] * len(groups)) in d, d
+        got = run(plan, xs)
+        for (n, b), y, r in zip(groups, got, refs):
+            for j in range(b):
+                assert rel(y[j], r[j]) <= TOL, (n, order, lines, j, rel(y[j], r[j]))
+    from paper_2006_08435_amd import _lib
+    L = _lib.lib()
+    assert L.fft3d_plan_set_group_schedule(plan.handle, 5, 0, 64) == _lib.FFT3D_E_INVALID_ARG
+    assert L.fft3d_plan_set_group_schedule(plan.handle, 0, 2, 64) == _lib.FFT3D_E_INVALID_ARG
+    assert L.fft3d_plan_set_group_schedule(plan.handle, 0, 0, 16) == _lib.FFT3D_E_INVALID_ARG
+
+
 def test_tuner_and_cache(F, tmp_path, monkeypatch):
     cache = tmp_path / "tune.json"
     monkeypatch.setenv("FFT3D_TUNE_CACHE", str(cache))
@@ -197,6 +226,10 @@ def test_tuner_and_cache(F, tmp_path, monkeypatch):
     d = json.loads(cache.read_text())
     (key, val), = d.items()
     assert val["threads"] in (0, 512, 1024, -512, -1024) and 1 <= val["chunk"] <= 8 and val["ms"] > 0
+    # per group: the radix order and z-tile width the tuner chose
+    kinds = [int(v) for v in val["radix"].split(",")]
+    zl = [int(v) for v in val["zlines"].split(",")]
+    assert len(kinds) == len(groups) and set(kinds) <= {0, 2} and len(zl) == len(groups) and set(zl) <= {32, 64}
     monkeypatch.delenv("FFT3D_TUNE")
     p2 = F.PlanMany(groups, -1)            # read back from the cache
     assert "tuned" in p2.describe()
