@@ -301,38 +301,45 @@ __device__ __forceinline__ void q16_last_stage_store(const float2* lds, const fl
     }
 }
 
-// The slab pass's input held for its first z stage straight from registers:
-// thread (x = tid % N, j = tid / N) holds the 16 inputs z = j + q N/16
-// (q < 16) of its radix-16 butterfly of line x, one scaled16 word each
-// (lanes along x: every load instruction reads whole rows), and the row
-// exponents.  When N is a multiple of 64 a wave shares j, so lane q < 16
-// loads the exponent of z = j + q N/16 and the others are taken from it
-// with readlane; otherwise every thread loads its 16 exponents.  Slab rows
-// (b, z, y) lie N rows apart from row0 = (b, 0, y); offsets are 32-bit from
-// the slab's base (a slab spans < 2^32 elements).  Threads from N N/16 on
-// (T is rounded up to whole waves) hold nothing.
-template <int N, int T>
+// A tile's input held for the first stage of the transform across its rows
+// straight from registers: thread (x = tid % N, j = tid / N) holds the 16
+// inputs e = j + q N/16 (q < 16) of its radix-16 butterfly of column x,
+// one scaled16 word each (lanes along x: every load instruction reads whole
+// rows), and the row exponents.  Row e starts RSTRIDE words and its
+// exponent ESTRIDE bytes after row 0 (slab pass: rows z of an xz-slab, N*N
+// and N; plane pass: rows y of an xy-plane, N and 1).  When N is a multiple
+// of 64 a wave shares j, so lane q < 16 loads the exponent of row
+// j + q N/16 and the others are taken from it with readlane; otherwise
+// every thread loads its 16 exponents.  Offsets are 32-bit from the tile's
+// base (a tile spans < 2^32 elements).  Threads from N N/16 on (T is
+// rounded up to whole waves) hold nothing.
+template <int N, int T, int RSTRIDE = N * N, int ESTRIDE = N>
 struct Q16ColRegs {
     static constexpr int M0 = N / 16, NB = N * M0;
     static_assert(T >= NB && (N % 64 != 0 || T == NB), "one first-stage butterfly per thread");
     static constexpr bool WAVE_J = N % 64 == 0;
     unsigned u[16];
     int e[WAVE_J ? 1 : 4];   // else the 16 exponents as bytes, four per word
+    // NT: streaming payload loads (see stream_plane)
+    template <bool NT = false>
     __device__ __forceinline__ void load(const unsigned* pay, const signed char* ex, int tid)
     {
         if (NB < T && tid >= NB) return;
         const int x = tid % N, j = tid / N;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) u[q] = pay[(unsigned)((j + M0 * q) * N * N + x)];
+        for (int q = 0; q < 16; ++q) {
+            if constexpr (NT) u[q] = __builtin_nontemporal_load(pay + (unsigned)((j + M0 * q) * RSTRIDE + x));
+            else u[q] = pay[(unsigned)((j + M0 * q) * RSTRIDE + x)];
+        }
         if constexpr (WAVE_J) {
             const int lane = tid & 63;
-            e[0] = lane < 16 ? (int)ex[(unsigned)((j + M0 * lane) * N)] : 0;
+            e[0] = lane < 16 ? (int)ex[(unsigned)((j + M0 * lane) * ESTRIDE)] : 0;
         } else {
 #pragma unroll
             for (int k = 0; k < 4; ++k) e[k] = 0;
 #pragma unroll
             for (int q = 0; q < 16; ++q)
-                e[q >> 2] |= ((int)(unsigned char)ex[(unsigned)((j + M0 * q) * N)]) << (8 * (q & 3));
+                e[q >> 2] |= ((int)(unsigned char)ex[(unsigned)((j + M0 * q) * ESTRIDE)]) << (8 * (q & 3));
         }
     }
     template <int FMT>
@@ -360,6 +367,54 @@ struct Q16ColRegs {
     }
 };
 
+// Last stage of the transform along the rows of an LDS tile (lines = rows,
+// row stride RS, elements contiguous), requantized straight from registers
+// row by row: output row r is stored as scaled16 at pay[r * N + x] with its
+// exponent at ex[r].  The stage is the last of a two-stage KIND-1 schedule
+// (radix 16, then R = N / 16), so every row has 16 butterflies; 16
+// consecutive lanes take the 16 butterflies of one row, find the row
+// maximum with a 16-lane reduction and store their R values each.  The
+// stage writes the positions it read, so no LDS barrier precedes it beyond
+// the one after the previous stage.
+template <int N, int S, int T, int RS, int FMT>
+__device__ __forceinline__ void q16_row_last_stage_store(const float2* lds, const float2* __restrict__ tw,
+                                                         unsigned* pay, signed char* ex, int tid)
+{
+    using P = Plan1D<N, 1>;
+    constexpr int ST = P::stages - 1, R = P::radix(ST), NS = P::ns(ST), M = N / R;
+    static_assert(P::stages == 2 && M == 16 && NS == 16, "a radix-16 stage then the last stage");
+    static_assert(T % 64 == 0, "row groups of 16 lanes stay inside waves");
+    constexpr int NB = N * M, IT = (NB + T - 1) / T;
+    const float2* __restrict__ tws = tw + P::tw_off(ST);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int b = tid + it * T;
+        const int j = b % M, row = b / M;
+        const bool live = NB % T == 0 || b < NB;   // uniform per 16-lane group
+        float2 v[R];
+        float m = 0.f;
+        if (live) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[q] = lds[row * RS + j + q * M];
+            const float2* __restrict__ w = tws + j * (R - 1);
+#pragma unroll
+            for (int q = 1; q < R; ++q) v[q] = cmul(v[q], w[q - 1]);
+            dft<R, S>(v);
+#pragma unroll
+            for (int q = 0; q < R; ++q) m = fmaxf(m, fmaxf(fabsf(v[q].x), fabsf(v[q].y)));
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 16));
+        if (live) {
+            const int e = row_exponent(m);
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                pay[(unsigned)(row * N + j + q * M)] = enc16<FMT>(ldexpf(v[q].x, -e)) | (enc16<FMT>(ldexpf(v[q].y, -e)) << 16);
+            if (j == 0) ex[(unsigned)row] = (signed char)e;
+        }
+    }
+}
+
 // Pass A: planes p = b * N + z, persistent over `planes` with the next plane
 // prefetched into registers.  Rows of the input (b, z, y) -> rows of the FP16
 // intermediate (b, z, ky).  NT: streaming input loads.
@@ -373,8 +428,36 @@ k_q16_plane(const unsigned* in_pay, const signed char* in_exp, unsigned* mid_pay
     __shared__ float2 lds[G::WORDS];
     __shared__ int lds_e[N];
     const int tid = threadIdx.x;
-    Q16Regs<N, N, T> regs;
     long p = blockIdx.x;
+    if constexpr (!MFMA && Plan1D<N, 1>::stages == 2) {
+        // y transform first, its radix-16 stage straight from the loaded
+        // registers; x transform last, requantized row by row from
+        // registers: three LDS sweeps and four barriers per plane instead
+        // of four and seven (the same DFT; rounding differs from the x-first
+        // order only at FP32 level).
+        Q16ColRegs<N, T, N, 1> cr;
+        if (p < planes) cr.template load<NT>(in_pay + p * N * N, in_exp + p * N, tid);
+        for (; p < planes; p += gridDim.x) {
+            cr.template stage0_to_lds<S, RS, FMT_IN>(lds, tid);   // y stage 0: lines = x
+            const long pn = p + gridDim.x;
+            if (pn < planes) cr.template load<NT>(in_pay + pn * N * N, in_exp + pn * N, tid);
+            __syncthreads();
+            {
+                const LdsAcc<1, RS> a{lds};                       // y stage 1 (the last of y), in place
+                fft_stage_p<Plan1D<N, 1>, 1, S, N, T, true, false>(a, a, tw, tid);
+            }
+            __syncthreads();
+            {
+                const LdsAcc<RS, 1> a{lds};                       // x stage 0: lines = rows
+                fft_stage_p<Plan1D<N, 1>, 0, S, N, T, true, true>(a, a, tw, tid);
+            }
+            __syncthreads();
+            q16_row_last_stage_store<N, S, T, RS, kFmtF16>(lds, tw, mid_pay + p * N * N, mid_exp + p * N, tid);
+            __syncthreads();   // the tile is read before the next plane's stage 0 writes it
+        }
+        return;
+    }
+    Q16Regs<N, N, T> regs;
     if (p < planes) regs.template load<false, NT>(in_pay + p * N * N, N, in_exp + p * N, 1, tid);
     for (; p < planes; p += gridDim.x) {
         regs.put_exponent(lds_e, tid);
