@@ -35,7 +35,7 @@ WORKLOADS = {
     "big256": (256, 4, 6000, "c2c 3D FFT, 4 grids of 256^3 (three-pass form), inverse then forward, complex64"),
     "big512": (512, 1, 6100, "c2c 3D FFT, one 512^3 grid (three-pass form), inverse then forward, complex64"),
 }
-EXTRA_WORKLOADS = ("mixed", "energy96", "fp16_128", "bf16_128", "pruned128", "real128", "copy_sweep")
+EXTRA_WORKLOADS = ("mixed", "energy96", "fp16_128", "bf16_128", "pruned128", "real128", "copy_sweep", "soak_mixed")
 
 
 def source_hash() -> str:
@@ -98,6 +98,8 @@ def main(argv=None):
 
     if args.workload == "copy_sweep":
         return bench_copy_sweep(args)
+    if args.workload == "soak_mixed":
+        return bench_soak(args)
     if args.workload == "mixed":
         return bench_mixed(args)
     if args.workload == "energy96":
@@ -407,6 +409,72 @@ def bench_copy_sweep(args):
                 "roofline": None, "cpu_baseline": None})
     print(json.dumps(rec))
     return 0
+
+
+def bench_soak(args):
+    """Bounded soak of the persistent kernel's cross-workgroup hand-off: the
+    mixed batch (256 x 64^3 + 48^3, 72^3, 96^3, 100^3, 120^3, inverse) run
+    back to back --steps times in each schedule that uses the persistent
+    kernel (all groups in it, and the hybrid split), every result compared
+    bit for bit with that schedule's first result on the device; stops at
+    the first mismatch.  fft3d_plan_check afterwards must report no expired
+    bounded wait."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2006_08435_amd as fft3d
+    from paper_2006_08435_amd import _lib
+    import workloads
+    groups = [(64, 256)] + [(n, 1) for n in workloads.MIXED_SIZES]
+    xs = [np.stack([workloads.sphere_grid(64, workloads.SEED_BATCH64 + j) for j in range(256)])]
+    xs += [workloads.sphere_grid(n, workloads.SEED_MIXED + n)[None] for n in workloads.MIXED_SIZES]
+    ins = [torch.from_numpy(x).cuda() for x in xs]
+    outs = [torch.empty_like(t) for t in ins]
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    iptr, optr = [t.data_ptr() for t in ins], [t.data_ptr() for t in outs]
+    L = _lib.lib()
+    runs = []
+    t_start = time.time()
+    for threads, chunk in ((1024, 2), (-1024, 2)):
+        plan = fft3d.PlanMany(groups, fft3d.FFT3D_INVERSE)
+        plan.set_schedule(threads, chunk)
+        plan.exec_ptrs(iptr, optr, sh)
+        torch.cuda.synchronize()
+        ref = [o.clone() for o in outs]
+        worst = 0.0
+        for (n, b), x, y in zip(groups, xs, ref):
+            j = b - 1
+            r = oracle.fft3d(x[j].astype(np.complex128), 1)
+            worst = max(worst, float(np.linalg.norm(y[j].cpu().numpy() - r) / np.linalg.norm(r)))
+        done, mismatch = 0, None
+        for k in range(args.steps):
+            for o in outs:
+                o.zero_()
+            plan.exec_ptrs(iptr, optr, sh)
+            same = all(torch.equal(a, b) for a, b in zip(ref, outs))
+            done += 1
+            if not same:
+                mismatch = k
+                break
+            if (k + 1) % 250 == 0:
+                print("[bench] soak threads=%d chunk=%d: %d execs identical" % (threads, chunk, k + 1),
+                      file=sys.stderr, flush=True)
+        check = L.fft3d_plan_check(plan.handle)
+        runs.append({"schedule": plan.describe(), "execs": done, "first_mismatch": mismatch,
+                     "plan_check": check, "plan_check_text": L.fft3d_strerror(check).decode(),
+                     "first_result_rel_l2_vs_fp64_max": worst})
+        if mismatch is not None or check != 0:
+            break
+    rec = _base_record(0.0, "execs", args, 0.0, "soak of the persistent hand-off, mixed batch 256 x 64^3 + "
+                       "48^3, 72^3, 96^3, 100^3, 120^3, inverse", {"groups": groups}, dtype="f32")
+    rec.update({"metric": "persistent-kernel soak: bitwise-identical back-to-back execs",
+                "value": sum(r["execs"] for r in runs), "runs": runs,
+                "mismatches": sum(r["first_mismatch"] is not None for r in runs),
+                "timeouts": sum(r["plan_check"] != 0 for r in runs),
+                "wall_s": round(time.time() - t_start, 1), "roofline": None, "cpu_baseline": None})
+    print(json.dumps(rec))
+    return 0 if rec["mismatches"] == 0 and rec["timeouts"] == 0 else 1
 
 
 def bench_mixed(args):

@@ -237,14 +237,18 @@ fft3d_plan_t fft3d_plan(int nx, int ny, int nz, int batch, int precision, int di
         if (env_flag("FFT3D_LOG")) std::fprintf(stderr, "fft3d_plan: %d XCDs, %d resident workgroups\n", nxcc, resident);
         p->fused_xcd = fused_mode() == 2 ? nxcc : 0;
         if (p->fused_xcd) {
-            // lag: the XCD's resident workgroups' worth of items, in grids
-            // (a lag of one grid, which would keep only two grids'
-            // intermediates in the XCD's L2, measured 1.8x slower at 64^3:
-            // the slab items wait).  FFT3D_FUSED_LAG overrides it.
+            // lag, in grids: every workgroup holds two claimed items (the
+            // current one and the next), so a slab item is claimed only
+            // after twice the XCD's resident workgroups' worth of items
+            // have been claimed since its grid's planes, plus two grids.
+            // Measured at 256 x 64^3 (lags 1, 2, 3, 5, 6, 8, 11, 16:
+            // 1.05, 0.77, 0.59, 0.34, 0.35, 0.36, 0.39, 0.42 ms per
+            // transform): shorter lags make slab items wait, longer ones
+            // keep more intermediates in flight.  FFT3D_FUSED_LAG overrides.
             const int res_x = fused_xcd_blocks_per_cu(nx) * cus;
             p->fused_grid = (int)(items < res_x ? items : res_x);
             const char* lg = std::getenv("FFT3D_FUSED_LAG");
-            p->fused_lag = lg && std::atoi(lg) > 0 ? std::atoi(lg) : (res_x / nxcc + nx - 1) / nx + 1;
+            p->fused_lag = lg && std::atoi(lg) > 0 ? std::atoi(lg) : (2 * (res_x / nxcc) + nx - 1) / nx + 2;
         }
         p->passes.push_back({Pass::kFusedK, nx, B, {}, p->tw_x});
     } else if (p->scheme == kCube) {
