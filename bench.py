@@ -85,6 +85,8 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of one workload buffer (for counter scaling)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="default workload only: skip the short runs of the 16-bit, mixed and energy forms")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs on a single MI355X; "
@@ -251,8 +253,51 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "source_hash": source_hash(),
     }
-    print(json.dumps(with_copy_peak(out)))
+    out = with_copy_peak(out)
+    if args.workload == "batch128" and not args.no_forms:
+        del a, b, c
+        torch.cuda.empty_cache()
+        out["forms"] = measure_forms(args)
+    print(json.dumps(out))
     return 0
+
+
+def measure_forms(args):
+    """Short runs (30 steps) of the other forms' workloads, so that one
+    default bench run measures them too: each as its own --workload would,
+    its summary kept (step time, GFLOP/s, roofline fraction, rel-L2 against
+    FP64 and the form's comparison figures); a failure is recorded, not
+    raised."""
+    import contextlib
+    import io
+    import torch
+    runs = (("fp16_128", lambda a: bench_q16(a, "fp16")), ("bf16_128", lambda a: bench_q16(a, "bf16")),
+            ("mixed", bench_mixed), ("energy96", bench_energy))
+    keep = ("speedup_vs_fp32", "radix16_engine_ms", "compare_ms", "times_ms", "plans")
+    forms = {}
+    for name, fn in runs:
+        sub = argparse.Namespace(**vars(args))
+        sub.workload, sub.steps, sub.warmup, sub.no_cpu_baseline = name, min(args.steps, 30), 5, True
+        buf = io.StringIO()
+        t0 = time.time()
+        try:
+            with contextlib.redirect_stdout(buf):
+                fn(sub)
+            rec = json.loads(buf.getvalue().strip().splitlines()[-1])
+            r = rec.get("roofline") or {}
+            forms[name] = dict({"workload": rec["config"]["workload"], "ms_per_step": rec["ms_per_step"],
+                                "value": rec["value"], "unit": rec["unit"], "steps": sub.steps,
+                                "roofline_frac": r.get("frac"), "traffic_ratio": r.get("traffic_ratio"),
+                                "rel_l2_vs_fp64": rec.get("rel_l2_vs_fp64")},
+                               **{k: rec[k] for k in keep if k in rec and k != "plans"})
+            if name == "mixed":
+                forms[name]["plan"] = rec["plans"]["many_tuned"]
+        except Exception as e:   # recorded in the line, the headline stays
+            forms[name] = {"error": "%s: %s" % (type(e).__name__, str(e)[:300])}
+        forms[name]["wall_s"] = round(time.time() - t0, 1)
+        print("[bench] form %s done in %.1fs" % (name, time.time() - t0), file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    return forms
 
 
 def _events():
