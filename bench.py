@@ -233,7 +233,8 @@ def main(argv=None):
                "sample": "%d grid transforms (cycling over the %d grids), inverse then forward, FP64 "
                          "recursive radix-5/3/2 FFT, %.1f s" % (done, batch, dt),
                "one_core_value": round(2 * 5.0 * n ** 3 * math.log2(n ** 3) * done1 / dt1 / 1e9, 3),
-               "one_core_sample": "%d grid transforms on 1 thread, %.1f s" % (done1, dt1)}
+               "one_core_sample": "%d grid transforms on 1 thread, %.1f s" % (done1, dt1),
+               "cpu_model": cpu_model(), "host_cpu_count": os.cpu_count()}
 
     out = {
         "metric": "3D FFT GFLOP/s (5N^3log2N^3/t) + HBM GB/s vs plain FP32, at rel-L2 err vs FP64",
@@ -298,6 +299,18 @@ def measure_forms(args):
         print("[bench] form %s done in %.1fs" % (name, time.time() - t0), file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     return forms
+
+
+def cpu_model():
+    """The host CPU's model name (first /proc/cpuinfo entry), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def _events():
