@@ -40,24 +40,109 @@ __device__ __forceinline__ float dec16(unsigned h)
     else return __builtin_bit_cast(float, h << 16);
 }
 
-// Round to nearest even into the 16-bit pattern.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// One payload word from a complex value: low half the real part, high half
+// the imaginary part, each rounded to nearest, ties to even (one packed
+// conversion instruction on gfx950 for either format).
 template <int FMT>
-__device__ __forceinline__ unsigned enc16(float x)
+__device__ __forceinline__ unsigned enc16x2(float re, float im)
 {
-    if constexpr (FMT == kFmtF16) {
-        return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)x);
-    } else {
-        const unsigned u = __builtin_bit_cast(unsigned, x);
-        return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    const f32x2_t f = {re, im};
+    if constexpr (FMT == kFmtF16) return __builtin_bit_cast(unsigned, __builtin_convertvector(f, f16x2_t));
+    else return __builtin_bit_cast(unsigned, __builtin_convertvector(f, bf16x2_t));
+}
+
+// max(m, |v.re|, |v.im|).  The NaN-propagating maximum compiles to
+// v_maximum3_f32 with absolute-value operand modifiers; maxnum (fmaxf)
+// would first quiet every operand with an extra instruction.
+__device__ __forceinline__ float absmax(float m, float2 v)
+{
+    return __builtin_elementwise_maximum(m, __builtin_elementwise_maximum(fabsf(v.x), fabsf(v.y)));
+}
+
+__device__ __forceinline__ unsigned fbits(float x) { return __builtin_bit_cast(unsigned, x); }
+
+// Maxima of absolute values run on their bit patterns: non-negative floats
+// order like their patterns as unsigned integers, and an integer maximum
+// takes a DPP operand in the same instruction (v_max_u32_dpp).
+
+// max(m, the pattern DPP control CTL moves into this lane); a lane outside
+// ROW_MASK reads 0, the identity of the maximum.
+template <int CTL, int ROW_MASK = 0xF>
+__device__ __forceinline__ unsigned dpp_max(unsigned m)
+{
+    return max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, CTL, ROW_MASK, 0xF, false));
+}
+
+// Maximum over each row of 16 lanes, in every lane of the row: lanes 1
+// apart, then 2 apart (quad permutations), then the two quads of each half
+// (half-row mirror), then the two halves (row mirror).  Every lane must be
+// active.
+__device__ __forceinline__ unsigned rowmax16(unsigned m)
+{
+    m = dpp_max<0xB1>(m);       // quad_perm [1,0,3,2]
+    m = dpp_max<0x4E>(m);       // quad_perm [2,3,0,1]
+    m = dpp_max<0x141>(m);      // row_half_mirror
+    return dpp_max<0x140>(m);   // row_mirror
+}
+
+// Maximum over the wave, wave-uniform: the row maxima, then row 0's into
+// row 1 and row 2's into row 3 (row_bcast15), then row 1's into rows 2 and
+// 3 (row_bcast31), so that lane 63 holds the maximum of all four rows.
+// Every lane must be active.
+__device__ __forceinline__ unsigned wavemax(unsigned m)
+{
+    m = rowmax16(m);
+    m = dpp_max<0x142, 0xA>(m);
+    m = dpp_max<0x143, 0xC>(m);
+    return (unsigned)__builtin_amdgcn_readlane((int)m, 63);
+}
+
+// Wave maxima of R = 4 or 8 values per lane at once, by halving exchanges
+// that also transpose: v_permlane32_swap pairs value i with i + R/2 (after
+// the maximum, lanes 0-31 hold value i's partial maximum and lanes 32-63
+// value i + R/2's), then v_permlane16_swap pairs the results again, so that
+// each row of 16 lanes holds one value's partial maximum; a row reduction
+// finishes them.  out[q]: the maximum of value q, wave-uniform.  Every lane
+// must be active.
+template <int R>
+__device__ __forceinline__ void wavemax_many(const unsigned (&m)[R], unsigned (&out)[R])
+{
+    static_assert(R == 4 || R == 8, "four or eight values");
+    constexpr int H = R / 2, Q = R / 4;
+    unsigned n[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) {   // n[i]: value i in lanes 0-31, value i + H in lanes 32-63
+        const auto sw = __builtin_amdgcn_permlane32_swap(m[i], m[i + H], false, false);
+        n[i] = max((unsigned)sw[0], (unsigned)sw[1]);
+    }
+    unsigned p[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {   // p[i]: values i, i + Q, i + H, i + H + Q in rows 0, 1, 2, 3
+        const auto sw = __builtin_amdgcn_permlane16_swap(n[i], n[i + Q], false, false);
+        p[i] = rowmax16(max((unsigned)sw[0], (unsigned)sw[1]));
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        out[i] = (unsigned)__builtin_amdgcn_readlane((int)p[i], 0);
+        out[i + Q] = (unsigned)__builtin_amdgcn_readlane((int)p[i], 16);
+        out[i + H] = (unsigned)__builtin_amdgcn_readlane((int)p[i], 32);
+        out[i + H + Q] = (unsigned)__builtin_amdgcn_readlane((int)p[i], 48);
     }
 }
 
-// Row exponent of the storage rule for a row maximum m >= 0.
-__device__ __forceinline__ int row_exponent(float m)
+// Row exponent of the storage rule for a finite row maximum m >= 0 given
+// by its bit pattern b: ilogb(m) - 14 = (biased exponent - 127) - 14 for a
+// normal m; every m below 2^-114 (subnormals included) clamps to -128, and
+// the largest finite m gives 113, so only the lower clamp is needed.
+__device__ __forceinline__ int row_exponent_bits(unsigned b)
 {
-    if (m == 0.f) return 0;
-    int e = __builtin_amdgcn_frexp_expf(m) - 1 - 14;   // ilogb(m) - 14
-    return e < -128 ? -128 : (e > 127 ? 127 : e);
+    if (b == 0) return 0;
+    const int e = (int)(b >> 23) - 127 - 14;
+    return e < -128 ? -128 : e;
 }
 
 template <int N>
@@ -130,16 +215,13 @@ __device__ __forceinline__ void q16_store_rows(const float2* lds, unsigned* pay,
         for (int k = 0; k < PER; ++k) {
             const int x = lane + 64 * k;
             v[k] = x < N ? lds[r * RS + x] : make_float2(0.f, 0.f);
-            m = fmaxf(m, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
+            m = absmax(m, v[k]);
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-        const int e = row_exponent(m);
+        const int e = row_exponent_bits(wavemax(fbits(m)));
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int x = lane + 64 * k;
-            if (x < N)
-                pay[r * rstride + x] = enc16<FMT>(ldexpf(v[k].x, -e)) | (enc16<FMT>(ldexpf(v[k].y, -e)) << 16);
+            if (x < N) pay[r * rstride + x] = enc16x2<FMT>(ldexpf(v[k].x, -e), ldexpf(v[k].y, -e));
         }
         if (lane == 0) ex[r * estride] = (signed char)e;
     }
@@ -284,18 +366,24 @@ __device__ __forceinline__ void q16_last_stage_store(const float2* lds, const fl
         for (int q = 1; q < R; ++q) v[it][q] = cmul(v[it][q], w[q - 1]);
         dft<R, S>(v[it]);
 #pragma unroll
-        for (int q = 0; q < R; ++q) m[q] = fmaxf(m[q], fmaxf(fabsf(v[it][q].x), fabsf(v[it][q].y)));
+        for (int q = 0; q < R; ++q) m[q] = absmax(m[q], v[it][q]);
+    }
+    unsigned mb[R], wm[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) mb[q] = fbits(m[q]);
+    if constexpr (R == 4 || R == 8) {
+        wavemax_many<R>(mb, wm);
+    } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) wm[q] = wavemax(mb[q]);
     }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) m[q] = fmaxf(m[q], __shfl_xor(m[q], o, 64));
-        const int r = j + q * NS, e = row_exponent(m[q]);
+        const int r = j + q * NS, e = row_exponent_bits(wm[q]);
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             const int x = lane + 64 * it;
-            pay[(unsigned)(r * rstride + x)] =
-                enc16<FMT>(ldexpf(v[it][q].x, -e)) | (enc16<FMT>(ldexpf(v[it][q].y, -e)) << 16);
+            pay[(unsigned)(r * rstride + x)] = enc16x2<FMT>(ldexpf(v[it][q].x, -e), ldexpf(v[it][q].y, -e));
         }
         if (lane == 0) ex[(unsigned)(r * estride)] = (signed char)e;
     }
@@ -326,10 +414,24 @@ struct Q16ColRegs {
     {
         if (NB < T && tid >= NB) return;
         const int x = tid % N, j = tid / N;
+        if constexpr (WAVE_J) {
+            // row addresses in scalar registers, the lane offset x in a vector one
+            // (a 32-bit byte offset, so that the load takes the scalar base + vector offset form)
+            const int js = __builtin_amdgcn_readfirstlane(j);
+            const unsigned bx = 4u * (unsigned)x;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            if constexpr (NT) u[q] = __builtin_nontemporal_load(pay + (unsigned)((j + M0 * q) * RSTRIDE + x));
-            else u[q] = pay[(unsigned)((j + M0 * q) * RSTRIDE + x)];
+            for (int q = 0; q < 16; ++q) {
+                const char* row = reinterpret_cast<const char*>(pay + (unsigned)((js + M0 * q) * RSTRIDE));
+                const unsigned* a = reinterpret_cast<const unsigned*>(row + bx);
+                if constexpr (NT) u[q] = __builtin_nontemporal_load(a);
+                else u[q] = *a;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                if constexpr (NT) u[q] = __builtin_nontemporal_load(pay + (unsigned)((j + M0 * q) * RSTRIDE + x));
+                else u[q] = pay[(unsigned)((j + M0 * q) * RSTRIDE + x)];
+            }
         }
         if constexpr (WAVE_J) {
             const int lane = tid & 63;
@@ -401,15 +503,14 @@ __device__ __forceinline__ void q16_row_last_stage_store(const float2* lds, cons
             for (int q = 1; q < R; ++q) v[q] = cmul(v[q], w[q - 1]);
             dft<R, S>(v);
 #pragma unroll
-            for (int q = 0; q < R; ++q) m = fmaxf(m, fmaxf(fabsf(v[q].x), fabsf(v[q].y)));
+            for (int q = 0; q < R; ++q) m = absmax(m, v[q]);
         }
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 16));
+        const unsigned mr = rowmax16(fbits(m));
         if (live) {
-            const int e = row_exponent(m);
+            const int e = row_exponent_bits(mr);
 #pragma unroll
             for (int q = 0; q < R; ++q)
-                pay[(unsigned)(row * N + j + q * M)] = enc16<FMT>(ldexpf(v[q].x, -e)) | (enc16<FMT>(ldexpf(v[q].y, -e)) << 16);
+                pay[(unsigned)(row * N + j + q * M)] = enc16x2<FMT>(ldexpf(v[q].x, -e), ldexpf(v[q].y, -e));
             if (j == 0) ex[(unsigned)row] = (signed char)e;
         }
     }
@@ -555,12 +656,9 @@ __global__ void __launch_bounds__(256) k_q16_quantize(const float2* in, long row
     if (r >= rows) return;
     const float2* row = in + r * C;
     float m = 0.f;
-    for (int x = lane; x < C; x += 64) m = fmaxf(m, fmaxf(fabsf(row[x].x), fabsf(row[x].y)));
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    const int e = row_exponent(m);
-    for (int x = lane; x < C; x += 64)
-        pay[r * C + x] = enc16<FMT>(ldexpf(row[x].x, -e)) | (enc16<FMT>(ldexpf(row[x].y, -e)) << 16);
+    for (int x = lane; x < C; x += 64) m = absmax(m, row[x]);
+    const int e = row_exponent_bits(wavemax(fbits(m)));
+    for (int x = lane; x < C; x += 64) pay[r * C + x] = enc16x2<FMT>(ldexpf(row[x].x, -e), ldexpf(row[x].y, -e));
     if (lane == 0) ex[r] = (signed char)e;
 }
 

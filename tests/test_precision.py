@@ -76,6 +76,21 @@ def test_dequantize_bit_exact(F, prec):
     assert np.array_equal(got.astype(np.complex128), want)
 
 
+def check_storage_rule(pay, ex, prec):
+    """Every row of a scaled16 array obeys the storage rule: with m the
+    largest |re| or |im| of the row's payload (the 16-bit values, exponent
+    not applied), m == 0 has exponent 0; otherwise 2^14 <= m <= 2^15 (2^15
+    when the row maximum rounded up to it), unless the exponent is clamped
+    at -128.  A row maximum taken over the wrong lanes or rows breaks it."""
+    v = oracle.q16_decode(pay, np.zeros_like(ex), FMT[prec])
+    m = np.maximum(np.abs(v.real), np.abs(v.imag)).max(axis=-1)
+    e = ex.astype(np.int64)
+    zero = m == 0
+    assert np.all(e[zero] == 0)
+    assert np.all(m[~zero] <= 2.0 ** 15)
+    assert np.all((m >= 2.0 ** 14) | (e == -128) | zero)
+
+
 def run_q16(F, x, prec, direction, inplace=False):
     b, n = x.shape[0], x.shape[-1]
     xt = torch.from_numpy(x).cuda()
@@ -104,6 +119,35 @@ def test_transform_within_bound(F, n, prec, direction):
     xin = oracle.q16_decode(pin, ein, FMT[prec])        # the input IS the 16-bit data
     got = oracle.q16_decode(pout, eout, FMT[prec])
     ref = oracle.fft3d(xin, direction)
+    for j in range(b):
+        r = rel(got[j], ref[j])
+        assert r <= TOL16, (n, prec, direction, j, r)
+    check_storage_rule(pout, eout, prec)
+
+
+@pytest.mark.parametrize("n", [32, 64, 96, 128])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("direction", [1, -1])
+def test_plane_pass_intermediate(F, n, prec, direction):
+    """The plane pass alone (fft3d_exec_pass 0): its intermediate, always
+    scaled FP16, is the 2D DFT over (y, x) of every z-plane of the
+    dequantized input, and obeys the storage rule row by row."""
+    from paper_2006_08435_amd import _lib
+    b = 2 if n <= 64 else 1
+    x = np.stack([workloads.sphere_grid(n, 700 + n + j) for j in range(b)])
+    xt = torch.from_numpy(x).cuda()
+    qin = F.quantize(xt, prec)
+    plan = F.Plan(n, n, n, b, prec, direction)
+    mid = torch.empty_like(qin)
+    s = torch.cuda.current_stream().cuda_stream
+    assert _lib.lib().fft3d_exec_pass(plan.handle, 0, qin.data_ptr(), mid.data_ptr(), s) == 0
+    torch.cuda.synchronize()
+    pin, ein = split(qin, x.shape)
+    pm, em = split(mid, x.shape)
+    check_storage_rule(pm, em, "fp16")
+    xin = oracle.q16_decode(pin, ein, FMT[prec]).reshape(b * n, 1, n, n)
+    ref = oracle.fft3d(xin, direction).reshape(x.shape)
+    got = oracle.q16_decode(pm, em, oracle.FMT_FP16)
     for j in range(b):
         r = rel(got[j], ref[j])
         assert r <= TOL16, (n, prec, direction, j, r)
@@ -144,6 +188,7 @@ def check_every_grid(pin, ein, pout, eout, prec, direction):
         r = rel(got, oracle.fft3d(xin, direction))
         assert r <= TOL16, (prec, direction, j, r)
         worst = max(worst, r)
+    check_storage_rule(pout, eout, prec)
     return worst
 
 
@@ -172,6 +217,7 @@ def test_mfma_engine_within_bound(F, n, prec, direction, monkeypatch):
     xin = oracle.q16_decode(pin, ein, FMT[prec])
     got = oracle.q16_decode(pout, eout, FMT[prec])
     assert rel(got, oracle.fft3d(xin, direction)) <= TOL16
+    check_storage_rule(pout, eout, prec)
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
