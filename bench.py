@@ -18,6 +18,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -38,26 +39,71 @@ WORKLOADS = {
 EXTRA_WORKLOADS = ("mixed", "energy96", "fp16_128", "bf16_128", "pruned128", "real128", "copy_sweep", "soak_mixed")
 
 
-def source_hash() -> str:
-    """Hash of the device-code sources (kernels and their launchers)."""
+CSRC = os.path.join(ROOT, "paper_2006_08435_amd", "csrc")
+# The translation units that launch each profiled kernel family, and the host
+# sources that choose every launch's grid and schedule.
+KERNEL_UNITS = {
+    "k_plane_pf": ("k_plane.hip", "k_variants.hip"), "k_plane_pruned": ("k_plane.hip",),
+    "k_axis_str": ("k_axis.hip", "k_axis_large.hip", "k_variants.hip"), "k_axis_row": ("k_axis.hip", "k_axis_large.hip"),
+    "k_axis_density": ("k_axis.hip",), "k_axis_energy": ("k_axis.hip",), "k_axis_hloc": ("k_axis.hip",),
+    "k_sum_partials": ("k_axis.hip",), "k_sphere_copy": ("k_axis.hip",), "k_fused_xcd": ("k_fused.hip",),
+    "k_many": ("k_many.hip",), "k_plane_r2c": ("k_real.hip",), "k_plane_c2r": ("k_real.hip",),
+    "k_stream_copy": ("k_copy.hip",), "k_q16_": ("k_q16.hip",),
+}
+HOST_UNITS = ("fft3d_api.cpp", "fft3d_many.cpp")
+
+
+def kernel_units(kernels):
+    """Translation units of the named kernels (profiler names) plus the host
+    sources; raises KeyError for a kernel family not listed above."""
+    units = set(HOST_UNITS)
+    for k in kernels:
+        fam = next((f for f in KERNEL_UNITS if k.startswith(f)), None)
+        if fam is None:
+            raise KeyError("no translation unit listed for kernel %r" % k)
+        units.update(KERNEL_UNITS[fam])
+    return sorted(units)
+
+
+def _include_closure(units):
+    seen, todo = set(), list(units)
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.add(f)
+        with open(os.path.join(CSRC, f)) as fh:
+            for line in fh:
+                m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+                if m:
+                    todo.append(os.path.normpath(os.path.relpath(os.path.join(CSRC, os.path.dirname(f), m.group(1)), CSRC)))
+    return sorted(seen)
+
+
+def source_hash(units=None) -> str:
+    """Hash of the device-code sources: every kernel source and header, or
+    (units given) those translation units and everything they include."""
     h = hashlib.sha1()
-    csrc = os.path.join(ROOT, "paper_2006_08435_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    if units is None:
+        files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp")))
+    else:
+        files = _include_closure(units)
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str, kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the summary is missing or was taken on different kernel code."""
+    None when the summary is missing or was taken on different kernel code
+    (its hash covers the sources of the kernels it lists, `units`)."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != source_hash():
+    if d.get("source_hash") != source_hash(d.get("units")):
         return None
     ks = d.get("kernels", {})
     k = ks.get(kernel)
