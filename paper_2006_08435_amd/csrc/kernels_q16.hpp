@@ -469,6 +469,140 @@ struct Q16ColRegs {
     }
 };
 
+// 2^d as an FP32 value for -126 <= d <= 127, from its bit pattern (exact;
+// wave-uniform callers compute it on the scalar unit without branches).
+__device__ __forceinline__ float pow2f(int d) { return __builtin_bit_cast(float, (unsigned)(d + 127) << 23); }
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+// The same first stage (radix 16 across the tile's rows, from registers) on
+// the matrix cores, straight from the binary16 payloads.  With x_q = h_q
+// 2^(e_q) the 16 inputs of butterfly j (payload h_q, row exponent e_q of
+// row j + M0 q),
+//   X_f = sum_q W^(f q) x_q = 2^E sum_q (W^(f q) 2^(e_q - E)) h_q,
+// E the largest exponent of the rows that are not all zero: the row
+// exponents fold into the DFT matrix (entries at most 1 in size, rounded to
+// binary16) and the payloads, as loaded, are the other operand.  An all-zero
+// row's exponent (0 by the storage rule) says nothing about its scale, so
+// it is left out of E and its matrix columns are 0.
+// v_mfma_f32_32x32x8_f16 takes 32 lines at a time: B (8 x 32) is 4
+// payload halves per lane, A (32 x 8) stacks the real-output rows 0-15 over
+// the imaginary-output rows 16-31, and four instructions accumulate the 32
+// real inputs (16 rows, re and im).  Lane l: line n = l % 32 of the block,
+// K half kb = l / 32; in instruction kk it holds rows q = 4 kk + 2 kb + t
+// (t < 2), one payload word (re, im) each, and the matching A entries for
+// output row l % 32; its results are frequencies f = 4 kb + c and
+// 8 + 4 kb + c (c < 4) of line n.  A wave takes one butterfly index j and 64
+// lines (two blocks).  Same layout conventions and interface as Q16ColRegs
+// (binary16 payloads only).
+template <int N, int T, int RSTRIDE = N * N, int ESTRIDE = N>
+struct Q16MfmaCols {
+    static constexpr int M0 = N / 16, WPJ = N / 64;
+    static_assert(N % 64 == 0 && T == N * M0, "a wave per butterfly index and 64 lines");
+    unsigned u[2][4][2];   // [line block][kk][t]
+    int ev;                // lane q < 16: exponent of row j + M0 q
+    unsigned ab[4][2];     // A entries before scaling: binary16 (re-input, im-input) pairs
+
+    template <int S>
+    __device__ __forceinline__ void init(int tid)
+    {
+        const int lane = tid & 63, m = lane & 31, kb = lane >> 5, f = m & 15;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int th = (f * (4 * kk + 2 * kb + t)) & 15;
+                const float c = cos16(th), s = (S > 0 ? 1.f : -1.f) * sin16(th);
+                const f16x2_t v = m < 16 ? f16x2_t{(_Float16)c, (_Float16)-s} : f16x2_t{(_Float16)s, (_Float16)c};
+                ab[kk][t] = __builtin_bit_cast(unsigned, v);
+            }
+    }
+    template <bool NT = false>
+    __device__ __forceinline__ void load(const unsigned* pay, const signed char* ex, int tid)
+    {
+        const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+        const int j = w / WPJ, x = 64 * (w % WPJ) + (lane & 31), kb = lane >> 5;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const unsigned* p = pay + (unsigned)((j + M0 * (4 * kk + 2 * kb + t)) * RSTRIDE + x + 32 * b);
+                    if constexpr (NT) u[b][kk][t] = __builtin_nontemporal_load(p);
+                    else u[b][kk][t] = *p;
+                }
+        ev = lane < 16 ? (int)ex[(unsigned)((j + M0 * lane) * ESTRIDE)] : 0;
+    }
+    template <int S, int ES, int FMT>
+    __device__ __forceinline__ void stage0_to_lds(float2* lds, int tid) const
+    {
+        static_assert(FMT == kFmtF16, "binary16 payloads");
+        const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+        const int j = w / WPJ, x = 64 * (w % WPJ) + (lane & 31), kb = lane >> 5;
+        // which rows hold a nonzero value on this wave's 64 lines (either sign of zero counts as zero)
+        bool nz[16];
+        int e[16];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const unsigned long long m =
+                    __builtin_amdgcn_ballot_w64(((u[0][kk][t] | u[1][kk][t]) & 0x7FFF7FFFu) != 0u);
+                nz[4 * kk + t] = (unsigned)m != 0u;
+                nz[4 * kk + 2 + t] = (unsigned)(m >> 32) != 0u;
+            }
+        // an all-zero row takes exponent -1000: it never sets E, and its
+        // scale 2^(-1000 - E) is 0
+        int E = -1000;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int eq = __builtin_amdgcn_readlane(ev, q);
+            e[q] = nz[q] ? eq : -1000;
+            E = e[q] > E ? e[q] : E;
+        }
+        half4_t a[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int q0 = 4 * kk + t, q1 = q0 + 2;
+                // 2^(e_q - E) (0 for an all-zero row), rounded to binary16 in
+                // both halves by one packed conversion: subnormal or 0 far below E
+                const int d0 = e[q0] - E, d1 = e[q1] - E;
+                const float sc = kb ? pow2f(d1 < -100 ? -100 : d1) : pow2f(d0 < -100 ? -100 : d0);
+                const f16x2_t v = __builtin_bit_cast(f16x2_t, ab[kk][t]) *
+                                  __builtin_convertvector(f32x2_t{sc, sc}, f16x2_t);
+                a[kk][2 * t] = v[0];
+                a[kk][2 * t + 1] = v[1];
+            }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            f32x16_t acc = {};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const unsigned w2[2] = {u[b][kk][0], u[b][kk][1]};
+                acc = __builtin_amdgcn_mfma_f32_32x32x8f16(a[kk], __builtin_bit_cast(half4_t, w2), acc, 0, 0, 0);
+            }
+            const int xb = x + 32 * b;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                lds[xb + (16 * j + 4 * kb + c) * ES] = make_float2(ldexpf(acc[c], E), ldexpf(acc[8 + c], E));
+                lds[xb + (16 * j + 8 + 4 * kb + c) * ES] = make_float2(ldexpf(acc[4 + c], E), ldexpf(acc[12 + c], E));
+            }
+        }
+    }
+};
+
+// Whether the first stage along the rows runs on the matrix cores from the
+// payloads (Q16MfmaCols) for this length and payload format.
+template <int N, int FMT>
+constexpr bool q16_mfma_cols(int T)
+{
+    return FMT == kFmtF16 && N % 64 == 0 && Plan1D<N, 1>::stages == 2 && T == N * (N / 16);
+}
+
 // Last stage of the transform along the rows of an LDS tile (lines = rows,
 // row stride RS, elements contiguous), requantized straight from registers
 // row by row: output row r is stored as scaled16 at pay[r * N + x] with its
@@ -530,13 +664,16 @@ k_q16_plane(const unsigned* in_pay, const signed char* in_exp, unsigned* mid_pay
     __shared__ int lds_e[N];
     const int tid = threadIdx.x;
     long p = blockIdx.x;
-    if constexpr (!MFMA && Plan1D<N, 1>::stages == 2) {
+    constexpr bool MC = MFMA && q16_mfma_cols<N, FMT_IN>(T);
+    if constexpr ((!MFMA || MC) && Plan1D<N, 1>::stages == 2) {
         // y transform first, its radix-16 stage straight from the loaded
-        // registers; x transform last, requantized row by row from
-        // registers: three LDS sweeps and four barriers per plane instead
-        // of four and seven (the same DFT; rounding differs from the x-first
-        // order only at FP32 level).
-        Q16ColRegs<N, T, N, 1> cr;
+        // registers (on the matrix cores with the MFMA engine); x transform
+        // last, requantized row by row from registers: three LDS sweeps and
+        // four barriers per plane instead of four and seven (the same DFT;
+        // rounding differs from the x-first order only at FP32 level).
+        using CR = typename std::conditional<MC, Q16MfmaCols<N, T, N, 1>, Q16ColRegs<N, T, N, 1>>::type;
+        CR cr;
+        if constexpr (MC) cr.template init<S>(tid);
         if (p < planes) cr.template load<NT>(in_pay + p * N * N, in_exp + p * N, tid);
         for (; p < planes; p += gridDim.x) {
             cr.template stage0_to_lds<S, RS, FMT_IN>(lds, tid);   // y stage 0: lines = x
@@ -599,11 +736,15 @@ k_q16_slab(const unsigned* mid_pay, const signed char* mid_exp, unsigned* out_pa
         return (s / N) * N * N + (s % N);
     };
     long s = blockIdx.x;
-    if constexpr (!MFMA && Plan1D<N, 1>::stages == 2) {
-        // First z stage straight from the loaded registers: one LDS write,
-        // one barrier, then the last stage (one LDS sweep and a barrier
-        // fewer per slab than staging the dequantized slab through LDS).
-        Q16ColRegs<N, T> cr;
+    constexpr bool MC = MFMA && q16_mfma_cols<N, kFmtF16>(T);
+    if constexpr ((!MFMA || MC) && Plan1D<N, 1>::stages == 2) {
+        // First z stage straight from the loaded registers (on the matrix
+        // cores with the MFMA engine): one LDS write, one barrier, then the
+        // last stage (one LDS sweep and a barrier fewer per slab than
+        // staging the dequantized slab through LDS).
+        using CR = typename std::conditional<MC, Q16MfmaCols<N, T>, Q16ColRegs<N, T>>::type;
+        CR cr;
+        if constexpr (MC) cr.template init<S>(tid);
         if (s < slabs) cr.load(mid_pay + row0(s) * N, mid_exp + row0(s), tid);
         for (; s < slabs; s += gridDim.x) {
             cr.template stage0_to_lds<S, RS, kFmtF16>(lds, tid);

@@ -153,6 +153,34 @@ def test_plane_pass_intermediate(F, n, prec, direction):
         assert r <= TOL16, (n, prec, direction, j, r)
 
 
+@pytest.mark.parametrize("engine", ["0", "1"])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("n", [64, 128])
+def test_power_of_two_scale_equivariance(F, engine, prec, n, monkeypatch):
+    """Scaling the input by 2^k (exponents only) scales every stage exactly:
+    the output payload is the same bit for bit and every nonzero row's
+    exponent moves by k, with either radix-16 engine (the matrix-core one
+    folds row exponents into its DFT matrix, relative to the largest
+    exponent of the rows that are not all zero)."""
+    monkeypatch.setenv("FFT3D_Q16_MFMA", engine)
+    x = workloads.sphere_grid(n, 4242 + n)[None]
+    p0, e0, outs = None, None, {}
+    rp, re_ = oracle.q16_encode(x, FMT[prec])
+    for k in (0, 40, -40):
+        plan = F.Plan(n, n, n, 1, prec, 1)
+        ek = np.where(np.any(rp & 0x7FFF, axis=(-2, -1)), re_.astype(np.int64) + k, 0).astype(np.int8)
+        out = plan.exec(join(rp, ek))
+        torch.cuda.synchronize()
+        outs[k] = split(out, x.shape)
+    pay0, ex0 = outs[0]
+    nzrow = np.any(pay0 & 0x7FFF, axis=(-2, -1))
+    for k in (40, -40):
+        pay, ex = outs[k]
+        assert np.array_equal(pay, pay0), (engine, prec, n, k)
+        assert np.array_equal(ex[nzrow].astype(np.int64), ex0[nzrow].astype(np.int64) + k), (engine, prec, n, k)
+        assert np.all(ex[~nzrow] == 0)
+
+
 def test_inplace_matches_out_of_place(F):
     x = np.stack([workloads.sphere_grid(64, 5 + j) for j in range(3)])
     _, _, _, p1, e1 = run_q16(F, x, "fp16", 1)
