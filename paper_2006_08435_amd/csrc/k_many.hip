@@ -49,6 +49,16 @@ size_t many_lds_bytes(int n, int threads)
     }
 }
 
-int many_per_item(int n, int threads) { return (threads == 1024 && n <= 64) ? 2 : 1; }
+int many_per_item(int n, int threads)
+{
+    switch (n) {
+#define FFT3D_MANY_PER(m)                                                                                  \
+    case m:                                                                                                \
+        return threads == 1024 ? many_per<m, 1024>() : many_per<m, 512>();
+        FFT3D_FOR_EACH_MANY_SIZE(FFT3D_MANY_PER)
+#undef FFT3D_MANY_PER
+    default: return 1;
+    }
+}
 
 }  // namespace fft3d
