@@ -4,7 +4,7 @@
 // the heterogeneous batches.  Kind 0 with 64-line tiles is the default pair
 // (plane_pf_fn / axis_str_fn).
 #include "kernels_fp32.hpp"
-#include "kernels_many.hpp"
+#include "many_sizes.hpp"
 #include "registry.hpp"
 
 namespace fft3d {

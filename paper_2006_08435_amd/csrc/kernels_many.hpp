@@ -14,47 +14,10 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels_fp32.hpp"
+#include "many_args.hpp"
+#include "many_sizes.hpp"
 
 namespace fft3d {
-
-constexpr int kMaxGroups = 16;
-
-struct ManyGrid {
-    int n;        // cubic size of this grid
-    int group;    // index into the exec's in/out pointer arrays
-    long offset;  // first element of the grid in its group's buffers
-};
-
-struct ManyArgs {
-    const float2* in[kMaxGroups];
-    float2* out[kMaxGroups];
-    const ManyGrid* grids;
-    const unsigned* items;
-    long nitems;
-    const float2* tw;    // twiddle tables of every size in the plan
-    const int* tw_off;   // tw_off[n]: offset of the length-n table
-    FusedCtl* ctl;
-    int chunk;
-    int ngrids;
-};
-
-// item = grid << 8 | slab << 7 | index
-__host__ __device__ constexpr unsigned many_item(unsigned grid, unsigned slab, unsigned idx)
-{
-    return grid << 8 | slab << 7 | idx;
-}
-
-// Sizes the heterogeneous kernel is compiled for.
-#define FFT3D_FOR_EACH_MANY_SIZE(X)                                            \
-    X(24) X(30) X(32) X(36) X(40) X(48) X(50) X(60) X(64) X(72) X(80) X(90)    \
-    X(96) X(100) X(120) X(128)
-
-constexpr bool many_size_supported(int n)
-{
-#define FFT3D_MANY_EQ(m) n == m ||
-    return FFT3D_FOR_EACH_MANY_SIZE(FFT3D_MANY_EQ) false;
-#undef FFT3D_MANY_EQ
-}
 
 struct ManyState {
     int pending;   // grid of this workgroup's last unpublished plane item, or -1

@@ -7,7 +7,8 @@
 
 #include "../../include/fft3d.h"
 #include "kernels_fp32.hpp"
-#include "kernels_many.hpp"
+#include "many_args.hpp"
+#include "many_sizes.hpp"
 #include "registry.hpp"
 #include "sched.hpp"
 
