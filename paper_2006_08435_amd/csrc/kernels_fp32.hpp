@@ -352,45 +352,42 @@ k_plane(const float2* in, float2* out, const float2* __restrict__ tw)
     plane_body<N, S, PlaneGeom<N>::T>(in + base, out + base, tw, lds, threadIdx.x);
 }
 
-// The y transform of a plane (lines = x, in LDS) with its last stage
-// stored as 16-byte pairs of adjacent lines.  In the last stage the 64
-// lanes of a wave take the wave's 64 lines in the order 0, 2, 4, ...
-// (lanes 0-31) then 1, 3, 5, ... (lanes 32-63); after the butterfly one
-// v_permlane32_swap per value component gives lane l < 32 the outputs of
-// lines x, x + 1 for the upper half of the butterfly's output rows and lane
-// l + 32 the same two lines for the lower half, each stored as one 16-byte
-// write (half the store instructions of one 8-byte value per lane, every
-// wave store still a run of whole rows).  The LDS reads of the stage cover
-// the same 64 consecutive positions per wave as before, conflict-free.
-template <int N, int K>
-constexpr bool plane_pairs_ok(int T)
+// Last stage of a length-N transform over L lines held in LDS (line x,
+// element e at src.load(x, e)), with the lines adjacent in global memory:
+// output element r of line x goes to out[x + r * es], stored as 16-byte
+// pairs of adjacent lines.  The 64 lanes of a wave take the wave's 64
+// lines in the order 0, 2, 4, ... (lanes 0-31) then 1, 3, 5, ... (lanes
+// 32-63); after the butterfly one v_permlane32_swap per value component
+// gives lane l < 32 the outputs of lines x, x + 1 for the upper half of the
+// butterfly's output elements and lane l + 32 the same two lines for the
+// lower half, each stored as one 16-byte write: half the store
+// instructions of one 8-byte value per lane, every wave store still whole
+// runs of adjacent lines.  The LDS reads cover the same 64 consecutive lines
+// per wave as the plain stage, conflict-free.
+template <int N, int L, int K>
+constexpr bool pairs_ok(int T)
 {
     using P = Plan1D<N, K>;
-    return N % 64 == 0 && P::radix(P::stages - 1) % 2 == 0 && (N * (N / P::radix(P::stages - 1))) % T == 0 &&
+    return L % 64 == 0 && P::radix(P::stages - 1) % 2 == 0 && (L * (N / P::radix(P::stages - 1))) % T == 0 &&
            T % 64 == 0;
 }
 
-template <int N, int S, int T, int K>
-__device__ __forceinline__ void plane_y_pairs(float2* lds, float2* out, const float2* __restrict__ tw, int tid)
+template <int N, int S, int L, int T, int K, class A>
+__device__ __forceinline__ void last_stage_pairs(const A& src, float2* out, long es, const float2* __restrict__ tw,
+                                                 int tid)
 {
     using P = Plan1D<N, K>;
-    constexpr int RS = PlaneGeom<N>::RS;
-    constexpr int ST = P::stages - 1, R = P::radix(ST), NS = P::ns(ST), M = N / R, NB = N * M, IT = NB / T;
-    static_assert(plane_pairs_ok<N, K>(T), "64-line waves, an even last radix, whole iterations");
-    const LdsAcc<1, RS> col{lds};
-    if constexpr (ST > 0) { fft_stage<N, 0, S, N, T, true, true, K>(col, col, tw, tid); __syncthreads(); }
-    if constexpr (ST > 1) { fft_stage<N, 1, S, N, T, true, true, K>(col, col, tw, tid); __syncthreads(); }
-    if constexpr (ST > 2) { fft_stage<N, 2, S, N, T, true, true, K>(col, col, tw, tid); __syncthreads(); }
-    static_assert(ST <= 3, "at most four stages");
+    constexpr int ST = P::stages - 1, R = P::radix(ST), NS = P::ns(ST), M = N / R, NB = L * M, IT = NB / T;
+    static_assert(pairs_ok<N, L, K>(T), "64-line waves, an even last radix, whole iterations");
     const float2* __restrict__ tws = tw + P::tw_off(ST);
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int b = tid + it * T, lane = b & 63, b0 = b - lane;
-        const int j = __builtin_amdgcn_readfirstlane(b0 / N);
-        const int xe = b0 % N + 2 * (lane & 31), x = xe + (lane >> 5);
+        const int j = __builtin_amdgcn_readfirstlane(b0 / L);
+        const int xe = b0 % L + 2 * (lane & 31), x = xe + (lane >> 5);
         float2 v[R];
 #pragma unroll
-        for (int q = 0; q < R; ++q) v[q] = col.load(x, j + q * M);
+        for (int q = 0; q < R; ++q) v[q] = src.load(x, j + q * M);
         if constexpr (NS > 1) {
             const float2* __restrict__ w = tws + (j % NS) * (R - 1);
 #pragma unroll
@@ -402,17 +399,30 @@ __device__ __forceinline__ void plane_y_pairs(float2* lds, float2* out, const fl
 #pragma unroll
         for (int k = 0; k < R / 2; ++k) {
             // new v[k + R/2] register: lanes 0-31 keep line xe, lanes 32-63 receive
-            // line xe of v[k]; new v[k] register: line xe + 1 of the same rows
+            // line xe of v[k]; new v[k] register: line xe + 1 of the same elements
             const auto re = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, v[k + R / 2].x),
                                                              __builtin_bit_cast(unsigned, v[k].x), false, false);
             const auto im = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, v[k + R / 2].y),
                                                              __builtin_bit_cast(unsigned, v[k].y), false, false);
-            const int row = base + (lower ? k : k + R / 2) * NS;
-            *reinterpret_cast<float4*>(out + row * N + xe) =
+            const long r = base + (lower ? k : k + R / 2) * NS;
+            *reinterpret_cast<float4*>(out + xe + r * es) =
                 make_float4(__builtin_bit_cast(float, (unsigned)re[0]), __builtin_bit_cast(float, (unsigned)im[0]),
                             __builtin_bit_cast(float, (unsigned)re[1]), __builtin_bit_cast(float, (unsigned)im[1]));
         }
     }
+}
+
+// All stages but the last of a length-N transform over L lines in LDS (in
+// place, each followed by a barrier), then the last one stored as pairs.
+template <int N, int S, int L, int T, int K, int FIRST, class A>
+__device__ __forceinline__ void tail_pairs(const A& a, float2* out, long es, const float2* __restrict__ tw, int tid)
+{
+    constexpr int ST = Plan1D<N, K>::stages - 1;
+    static_assert(ST - FIRST <= 3, "at most three stages before the last");
+    if constexpr (FIRST < ST) { fft_stage<N, FIRST, S, L, T, true, true, K>(a, a, tw, tid); __syncthreads(); }
+    if constexpr (FIRST + 1 < ST) { fft_stage<N, FIRST + 1, S, L, T, true, true, K>(a, a, tw, tid); __syncthreads(); }
+    if constexpr (FIRST + 2 < ST) { fft_stage<N, FIRST + 2, S, L, T, true, true, K>(a, a, tw, tid); __syncthreads(); }
+    last_stage_pairs<N, S, L, T, K>(a, out, es, tw, tid);
 }
 
 // Persistent form of the plane pass: workgroup w transforms planes
@@ -453,8 +463,8 @@ k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long pl
             if constexpr (SCALE) regs.load_factors(vr, V + (pn % nz) * N * N, tid);
         }
         fft_lds_all<N, S, N, T, RS, 1, K>(lds, tw, tid);
-        if constexpr (plane_pairs_ok<N, K>(T)) {
-            plane_y_pairs<N, S, T, K>(lds, out + p * N * N, tw, tid);
+        if constexpr (pairs_ok<N, N, K>(T)) {   // y transform: lines = x, rows y N apart
+            tail_pairs<N, S, N, T, K, 0>(LdsAcc<1, RS>{lds}, out + p * N * N, (long)N, tw, tid);
         } else {
             const LdsAcc<1, RS> col{lds};
             const PlaneColOut<N> dst{out + p * N * N};
@@ -1116,6 +1126,8 @@ k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap
             const LdsAcc<1, G::LP> a{lds};
             fft_stage<N, 0, S, L, T, true, false, K>(g, a, tw, tid, valid);
             __syncthreads();
+            // (16-byte paired stores, as in the plane pass, measured no faster here:
+            // this pass already runs at the streaming-copy rate)
             run_tail<N, S, L, T, 1, false, K>(a, g, tw, tid, valid);
         }
     }
