@@ -50,18 +50,24 @@ KERNEL_UNITS = {
     "k_many": ("k_many.hip",), "k_plane_r2c": ("k_real.hip",), "k_plane_c2r": ("k_real.hip",),
     "k_stream_copy": ("k_copy.hip",), "k_q16_": ("k_q16.hip",),
 }
-HOST_UNITS = ("fft3d_api.cpp", "fft3d_many.cpp")
+HOST_UNITS = ("fft3d_api.cpp",)
+# the batched form's planner (work lists, schedules, tuner) launches these too
+MANY_HOST_UNITS = ("fft3d_many.cpp",)
 
 
 def kernel_units(kernels):
     """Translation units of the named kernels (profiler names) plus the host
-    sources; raises KeyError for a kernel family not listed above."""
+    sources that plan their launches (the batched form's planner when the
+    persistent kernel is among them); raises KeyError for a kernel family not
+    listed above."""
     units = set(HOST_UNITS)
     for k in kernels:
         fam = next((f for f in KERNEL_UNITS if k.startswith(f)), None)
         if fam is None:
             raise KeyError("no translation unit listed for kernel %r" % k)
         units.update(KERNEL_UNITS[fam])
+        if fam == "k_many":
+            units.update(MANY_HOST_UNITS)
     return sorted(units)
 
 
