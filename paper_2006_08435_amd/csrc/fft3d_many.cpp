@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <deque>
 #include <fstream>
 #include <map>
@@ -48,7 +49,12 @@ std::vector<unsigned> build_items(const std::vector<ManyGrid>& grids, int thread
             ready.pop_front();
         }
     };
-    for (int g = 0; g < (int)grids.size(); ++g) {
+    // largest grids first: their plane-then-slab chains are the longest, and
+    // the many short items of the small grids fill the end of the list
+    std::vector<int> order(grids.size());
+    for (int g = 0; g < (int)grids.size(); ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return grids[a].n > grids[b].n; });
+    for (const int g : order) {
         if (skip && skip[grids[g].group]) continue;
         const int n = grids[g].n, per = many_per_item(n, threads);
         for (int i = 0; i < n; i += per) {
@@ -492,7 +498,7 @@ fft3d_plan_t fft3d_plan_many(int count, const int* nx, const int* ny, const int*
         set_error(FFT3D_E_ALLOC);
         return nullptr;
     }
-    int threads = 1024, chunk = 2;
+    int threads = 1024, chunk = 1;
     for (int g = 0; g < count; ++g) mp.zlines[g] = kAxisLines;
     const bool cached = cache_lookup(cache_key(p), count, threads, chunk, mp.kind, mp.zlines);
     int rc = apply_schedule(p, threads, chunk);
