@@ -81,6 +81,18 @@ constexpr bool stream_plane(int n) { return n >= 16; }
 // passes; below this many bytes per pass (a single 128^3 grid is 16 MB) the
 // default policy is faster.
 constexpr long kStreamMinBytes = 32L << 20;
+// The streamed plane passes with paired 16-byte stores (N = 64, 128) store
+// the output of their first planes with the streaming policy too, all but
+// the last kPlaneCachedTail bytes: the planes written first leave the
+// Infinity Cache (256 MB) before the z pass, which reads the last-written
+// first, reaches them, and caching them only displaces the tail it does
+// find there.
+constexpr long kPlaneCachedTail = 320L << 20;
+
+__host__ __device__ constexpr long streamed_store_planes(long planes, long plane_bytes)
+{
+    return planes > kPlaneCachedTail / plane_bytes ? planes - kPlaneCachedTail / plane_bytes : 0;
+}
 
 // Global memory with a runtime element stride and a per-thread line base
 // (the line index passed in is ignored; the caller has folded it into base).

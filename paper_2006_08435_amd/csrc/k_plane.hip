@@ -17,18 +17,20 @@ static hipError_t launch_plane_pf(const float2* in, float2* out, const float2* t
 {
     const dim3 g((unsigned)grid), b(PlaneGeom<N>::T);
     if constexpr (stream_plane(N)) {
-        if (stream && planes * N * N * (long)sizeof(float2) >= kStreamMinBytes) {
+        constexpr long pb = (long)N * N * sizeof(float2);
+        if (stream && planes * pb >= kStreamMinBytes) {
+            const long ntp = streamed_store_planes(planes, pb);   // used where the stores are paired
             if (scale)
-                hipLaunchKernelGGL((k_plane_pf<N, S, true, true>), g, b, 0, st, in, out, tw, planes, V, gE, nz);
+                hipLaunchKernelGGL((k_plane_pf<N, S, true, true>), g, b, 0, st, in, out, tw, planes, V, gE, nz, ntp);
             else
-                hipLaunchKernelGGL((k_plane_pf<N, S, false, true>), g, b, 0, st, in, out, tw, planes, V, gE, nz);
+                hipLaunchKernelGGL((k_plane_pf<N, S, false, true>), g, b, 0, st, in, out, tw, planes, V, gE, nz, ntp);
             return hipGetLastError();
         }
     }
     if (scale)
-        hipLaunchKernelGGL((k_plane_pf<N, S, true>), g, b, 0, st, in, out, tw, planes, V, gE, nz);
+        hipLaunchKernelGGL((k_plane_pf<N, S, true>), g, b, 0, st, in, out, tw, planes, V, gE, nz, 0L);
     else
-        hipLaunchKernelGGL((k_plane_pf<N, S, false>), g, b, 0, st, in, out, tw, planes, V, gE, nz);
+        hipLaunchKernelGGL((k_plane_pf<N, S, false>), g, b, 0, st, in, out, tw, planes, V, gE, nz, 0L);
     return hipGetLastError();
 }
 

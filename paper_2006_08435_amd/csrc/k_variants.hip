@@ -14,10 +14,13 @@ static hipError_t launch_plane_v(const float2* in, float2* out, const float2* tw
                                  hipStream_t st)
 {
     const dim3 g((unsigned)grid), b(PlaneGeom<N>::T);
-    if (stream && planes * N * N * (long)sizeof(float2) >= kStreamMinBytes)
-        hipLaunchKernelGGL((k_plane_pf<N, S, false, true, K>), g, b, 0, st, in, out, tw, planes, nullptr, nullptr, N);
+    constexpr long pb = (long)N * N * sizeof(float2);
+    if (stream && planes * pb >= kStreamMinBytes)
+        hipLaunchKernelGGL((k_plane_pf<N, S, false, true, K>), g, b, 0, st, in, out, tw, planes, nullptr, nullptr, N,
+                           streamed_store_planes(planes, pb));
     else
-        hipLaunchKernelGGL((k_plane_pf<N, S, false, false, K>), g, b, 0, st, in, out, tw, planes, nullptr, nullptr, N);
+        hipLaunchKernelGGL((k_plane_pf<N, S, false, false, K>), g, b, 0, st, in, out, tw, planes, nullptr, nullptr, N,
+                           0L);
     return hipGetLastError();
 }
 

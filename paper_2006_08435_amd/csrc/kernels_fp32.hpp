@@ -372,7 +372,7 @@ constexpr bool pairs_ok(int T)
            T % 64 == 0;
 }
 
-template <int N, int S, int L, int T, int K, class A>
+template <int N, int S, int L, int T, int K, bool NTS = false, class A>
 __device__ __forceinline__ void last_stage_pairs(const A& src, float2* out, long es, const float2* __restrict__ tw,
                                                  int tid)
 {
@@ -405,16 +405,19 @@ __device__ __forceinline__ void last_stage_pairs(const A& src, float2* out, long
             const auto im = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, v[k + R / 2].y),
                                                              __builtin_bit_cast(unsigned, v[k].y), false, false);
             const long r = base + (lower ? k : k + R / 2) * NS;
-            *reinterpret_cast<float4*>(out + xe + r * es) =
-                make_float4(__builtin_bit_cast(float, (unsigned)re[0]), __builtin_bit_cast(float, (unsigned)im[0]),
-                            __builtin_bit_cast(float, (unsigned)re[1]), __builtin_bit_cast(float, (unsigned)im[1]));
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            const f4v val = {__builtin_bit_cast(float, (unsigned)re[0]), __builtin_bit_cast(float, (unsigned)im[0]),
+                             __builtin_bit_cast(float, (unsigned)re[1]), __builtin_bit_cast(float, (unsigned)im[1])};
+            f4v* dst = reinterpret_cast<f4v*>(out + xe + r * es);
+            if constexpr (NTS) __builtin_nontemporal_store(val, dst);   // streaming store
+            else *dst = val;
         }
     }
 }
 
 // All stages but the last of a length-N transform over L lines in LDS (in
 // place, each followed by a barrier), then the last one stored as pairs.
-template <int N, int S, int L, int T, int K, int FIRST, class A>
+template <int N, int S, int L, int T, int K, int FIRST, bool NTS = false, class A>
 __device__ __forceinline__ void tail_pairs(const A& a, float2* out, long es, const float2* __restrict__ tw, int tid)
 {
     constexpr int ST = Plan1D<N, K>::stages - 1;
@@ -422,7 +425,7 @@ __device__ __forceinline__ void tail_pairs(const A& a, float2* out, long es, con
     if constexpr (FIRST < ST) { fft_stage<N, FIRST, S, L, T, true, true, K>(a, a, tw, tid); __syncthreads(); }
     if constexpr (FIRST + 1 < ST) { fft_stage<N, FIRST + 1, S, L, T, true, true, K>(a, a, tw, tid); __syncthreads(); }
     if constexpr (FIRST + 2 < ST) { fft_stage<N, FIRST + 2, S, L, T, true, true, K>(a, a, tw, tid); __syncthreads(); }
-    last_stage_pairs<N, S, L, T, K>(a, out, es, tw, tid);
+    last_stage_pairs<N, S, L, T, K, NTS>(a, out, es, tw, tid);
 }
 
 // Persistent form of the plane pass: workgroup w transforms planes
@@ -432,14 +435,16 @@ __device__ __forceinline__ void tail_pairs(const A& a, float2* out, long es, con
 // SCALE: every input value at grid position r is first multiplied by the real
 // factor 2 * gE[0] * V[r] (V: one [nz][N][N] grid shared by the batch) -- the
 // prologue of the energy gradient.
-// NT: streaming plane loads (see stream_plane); the stores keep the default
-// policy so that the z pass after it finds their last part in the caches.
+// NT: streaming plane loads (see stream_plane); planes below nt_planes
+// (streamed_store_planes) also stream their stores, the rest keep the
+// default policy so that the z pass after it finds the last part of the
+// output in the caches.
 // K: schedule kind of both 1D transforms (0 default, 2 the tuner's
 // alternative order; the twiddle table must be of the same kind).
 template <int N, int S, bool SCALE = false, bool NT = false, int K = 0>
 __global__ void __launch_bounds__(PlaneGeom<N>::T)
 k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long planes, const float* __restrict__ V,
-           const double* __restrict__ gE, int nz)
+           const double* __restrict__ gE, int nz, long nt_planes)
 {
     constexpr int T = PlaneGeom<N>::T, RS = PlaneGeom<N>::RS;
     __shared__ float2 lds[PlaneGeom<N>::WORDS];
@@ -464,7 +469,10 @@ k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long pl
         }
         fft_lds_all<N, S, N, T, RS, 1, K>(lds, tw, tid);
         if constexpr (pairs_ok<N, N, K>(T)) {   // y transform: lines = x, rows y N apart
-            tail_pairs<N, S, N, T, K, 0>(LdsAcc<1, RS>{lds}, out + p * N * N, (long)N, tw, tid);
+            if (NT && p < nt_planes)   // uniform: the store policy is chosen per plane
+                tail_pairs<N, S, N, T, K, 0, NT>(LdsAcc<1, RS>{lds}, out + p * N * N, (long)N, tw, tid);
+            else
+                tail_pairs<N, S, N, T, K, 0>(LdsAcc<1, RS>{lds}, out + p * N * N, (long)N, tw, tid);
         } else {
             const LdsAcc<1, RS> col{lds};
             const PlaneColOut<N> dst{out + p * N * N};
