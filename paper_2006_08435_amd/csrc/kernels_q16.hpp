@@ -474,6 +474,7 @@ struct Q16ColRegs {
 __device__ __forceinline__ float pow2f(int d) { return __builtin_bit_cast(float, (unsigned)(d + 127) << 23); }
 
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef short bf16x4_bits_t __attribute__((ext_vector_type(4)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 // The same first stage (radix 16 across the tile's rows, from registers) on
@@ -494,19 +495,31 @@ typedef float f32x16_t __attribute__((ext_vector_type(16)));
 // (t < 2), one payload word (re, im) each, and the matching A entries for
 // output row l % 32; its results are frequencies f = 4 kb + c and
 // 8 + 4 kb + c (c < 4) of line n.  A wave takes one butterfly index j and 64
-// lines (two blocks).  Same layout conventions and interface as Q16ColRegs
-// (binary16 payloads only).
-template <int N, int T, int RSTRIDE = N * N, int ESTRIDE = N>
+// lines (two blocks).  Same layout conventions and interface as Q16ColRegs.
+// bfloat16 payloads (PF = kFmtBF16) go to v_mfma_f32_32x32x8_bf16 as loaded
+// (same operand layout); the matrix is then the sum of two bfloat16
+// matrices, its entries rounded to bfloat16 and the remainders rounded
+// again (about 16 significant bits, more than the binary16 matrix's 11),
+// and each product pair accumulates both.  The remainders depend on the
+// lane only; they sit in a 2 KB LDS table (kMfmaLoWords words, filled by
+// wave 0 in init, read after the caller's next barrier) rather than in 8
+// more registers per lane.
+constexpr int kMfmaLoWords = 8 * 64;
+
+template <int N, int T, int RSTRIDE = N * N, int ESTRIDE = N, int PF = kFmtF16>
 struct Q16MfmaCols {
     static constexpr int M0 = N / 16, WPJ = N / 64;
     static_assert(N % 64 == 0 && T == N * M0, "a wave per butterfly index and 64 lines");
     unsigned u[2][4][2];   // [line block][kk][t]
     int ev;                // lane q < 16: exponent of row j + M0 q
-    unsigned ab[4][2];     // A entries before scaling: binary16 (re-input, im-input) pairs
+    unsigned ab[4][2];     // A entries before scaling: 16-bit (re-input, im-input) pairs in the payload format
+    const unsigned* lo;    // bfloat16 payloads: the entries' remainders, word (2 kk + t) * 64 + lane
 
+    // lo_tab: kMfmaLoWords words of LDS (bfloat16 payloads only)
     template <int S>
-    __device__ __forceinline__ void init(int tid)
+    __device__ __forceinline__ void init(int tid, unsigned* lo_tab = nullptr)
     {
+        lo = lo_tab;
         const int lane = tid & 63, m = lane & 31, kb = lane >> 5, f = m & 15;
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
@@ -514,8 +527,17 @@ struct Q16MfmaCols {
             for (int t = 0; t < 2; ++t) {
                 const int th = (f * (4 * kk + 2 * kb + t)) & 15;
                 const float c = cos16(th), s = (S > 0 ? 1.f : -1.f) * sin16(th);
-                const f16x2_t v = m < 16 ? f16x2_t{(_Float16)c, (_Float16)-s} : f16x2_t{(_Float16)s, (_Float16)c};
-                ab[kk][t] = __builtin_bit_cast(unsigned, v);
+                const float v0 = m < 16 ? c : s, v1 = m < 16 ? -s : c;
+                if constexpr (PF == kFmtF16) {
+                    ab[kk][t] = enc16x2<kFmtF16>(v0, v1);
+                } else {
+                    const unsigned hi = enc16x2<kFmtBF16>(v0, v1);
+                    ab[kk][t] = hi;
+                    if (tid < 64)
+                        lo_tab[(2 * kk + t) * 64 + lane] =
+                            enc16x2<kFmtBF16>(v0 - __builtin_bit_cast(float, hi << 16),
+                                              v1 - __builtin_bit_cast(float, hi & 0xFFFF0000u));
+                }
             }
     }
     template <bool NT = false>
@@ -538,7 +560,7 @@ struct Q16MfmaCols {
     template <int S, int ES, int FMT>
     __device__ __forceinline__ void stage0_to_lds(float2* lds, int tid) const
     {
-        static_assert(FMT == kFmtF16, "binary16 payloads");
+        static_assert(FMT == PF, "the payload format the matrix was built for");
         const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
         const int j = w / WPJ, x = 64 * (w % WPJ) + (lane & 31), kb = lane >> 5;
         // which rows hold a nonzero value on this wave's 64 lines (either sign of zero counts as zero)
@@ -563,19 +585,32 @@ struct Q16MfmaCols {
             E = e[q] > E ? e[q] : E;
         }
         half4_t a[4];
+        unsigned ah[4][2], al[4][2];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 const int q0 = 4 * kk + t, q1 = q0 + 2;
-                // 2^(e_q - E) (0 for an all-zero row), rounded to binary16 in
-                // both halves by one packed conversion: subnormal or 0 far below E
                 const int d0 = e[q0] - E, d1 = e[q1] - E;
-                const float sc = kb ? pow2f(d1 < -100 ? -100 : d1) : pow2f(d0 < -100 ? -100 : d0);
-                const f16x2_t v = __builtin_bit_cast(f16x2_t, ab[kk][t]) *
-                                  __builtin_convertvector(f32x2_t{sc, sc}, f16x2_t);
-                a[kk][2 * t] = v[0];
-                a[kk][2 * t + 1] = v[1];
+                const int d = kb ? d1 : d0;
+                if constexpr (PF == kFmtF16) {
+                    // 2^(e_q - E) (0 for an all-zero row), rounded to binary16 in
+                    // both halves by one packed conversion: subnormal or 0 far below E
+                    const float sc = kb ? pow2f(d1 < -100 ? -100 : d1) : pow2f(d0 < -100 ? -100 : d0);
+                    const f16x2_t v = __builtin_bit_cast(f16x2_t, ab[kk][t]) *
+                                      __builtin_convertvector(f32x2_t{sc, sc}, f16x2_t);
+                    a[kk][2 * t] = v[0];
+                    a[kk][2 * t + 1] = v[1];
+                } else {
+                    // 2^(e_q - E), exact in bfloat16; 0 for an all-zero row and
+                    // below 2^-100 (far under FP32 rounding of the sum)
+                    const float sc = d < -100 ? 0.f : pow2f(d < -100 ? -100 : d);
+                    const unsigned h = ab[kk][t], l = lo[(2 * kk + t) * 64 + lane];
+                    ah[kk][t] = enc16x2<kFmtBF16>(sc * __builtin_bit_cast(float, h << 16),
+                                                  sc * __builtin_bit_cast(float, h & 0xFFFF0000u));
+                    al[kk][t] = enc16x2<kFmtBF16>(sc * __builtin_bit_cast(float, l << 16),
+                                                  sc * __builtin_bit_cast(float, l & 0xFFFF0000u));
+                }
             }
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
@@ -583,7 +618,16 @@ struct Q16MfmaCols {
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
                 const unsigned w2[2] = {u[b][kk][0], u[b][kk][1]};
-                acc = __builtin_amdgcn_mfma_f32_32x32x8f16(a[kk], __builtin_bit_cast(half4_t, w2), acc, 0, 0, 0);
+                if constexpr (PF == kFmtF16) {
+                    acc = __builtin_amdgcn_mfma_f32_32x32x8f16(a[kk], __builtin_bit_cast(half4_t, w2), acc, 0, 0, 0);
+                } else {
+                    const bf16x4_bits_t bv = __builtin_bit_cast(bf16x4_bits_t, w2);
+                    const unsigned h2[2] = {ah[kk][0], ah[kk][1]}, l2[2] = {al[kk][0], al[kk][1]};
+                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(__builtin_bit_cast(bf16x4_bits_t, h2), bv, acc, 0,
+                                                                   0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(__builtin_bit_cast(bf16x4_bits_t, l2), bv, acc, 0,
+                                                                   0, 0);
+                }
             }
             const int xb = x + 32 * b;
 #pragma unroll
@@ -600,7 +644,7 @@ struct Q16MfmaCols {
 template <int N, int FMT>
 constexpr bool q16_mfma_cols(int T)
 {
-    return FMT == kFmtF16 && N % 64 == 0 && Plan1D<N, 1>::stages == 2 && T == N * (N / 16);
+    return (FMT == kFmtF16 || FMT == kFmtBF16) && N % 64 == 0 && Plan1D<N, 1>::stages == 2 && T == N * (N / 16);
 }
 
 // Last stage of the transform along the rows of an LDS tile (lines = rows,
@@ -671,9 +715,15 @@ k_q16_plane(const unsigned* in_pay, const signed char* in_exp, unsigned* mid_pay
         // last, requantized row by row from registers: three LDS sweeps and
         // four barriers per plane instead of four and seven (the same DFT;
         // rounding differs from the x-first order only at FP32 level).
-        using CR = typename std::conditional<MC, Q16MfmaCols<N, T, N, 1>, Q16ColRegs<N, T, N, 1>>::type;
+        using CR = typename std::conditional<MC, Q16MfmaCols<N, T, N, 1, FMT_IN>, Q16ColRegs<N, T, N, 1>>::type;
         CR cr;
-        if constexpr (MC) cr.template init<S>(tid);
+        if constexpr (MC && FMT_IN == kFmtBF16) {
+            __shared__ unsigned lo_tab[kMfmaLoWords];
+            cr.template init<S>(tid, lo_tab);
+            __syncthreads();
+        } else if constexpr (MC) {
+            cr.template init<S>(tid);
+        }
         if (p < planes) cr.template load<NT>(in_pay + p * N * N, in_exp + p * N, tid);
         for (; p < planes; p += gridDim.x) {
             cr.template stage0_to_lds<S, RS, FMT_IN>(lds, tid);   // y stage 0: lines = x

@@ -259,3 +259,39 @@ def test_mfma_batch_32x128(F, prec, monkeypatch):
         plan, pin, ein, pout, eout = run_q16(F, x, prec, direction)
         assert "radix-16 on MFMA" in plan.describe()
         check_every_grid(pin, ein, pout, eout, prec, direction)
+
+
+def bf16_bits(a):
+    """bfloat16 bit patterns of float32 values, rounded to nearest even
+    (finite values)."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+@pytest.mark.parametrize("engine", ["0", "1"])
+@pytest.mark.parametrize("n", [64, 128])
+def test_bf16_payloads_any_range(F, engine, n, monkeypatch):
+    """bfloat16 input as a caller may hand it over, not in the storage rule's
+    normal form: zero exponents with rows 2^-60 ... 2^60 in size, and plain
+    payloads whose row exponents lie up to 130 apart (rows more than 100 below
+    the largest, which the matrix-core engine drops, weigh less than FP32
+    rounding).  Both radix-16 engines against the oracle on the same input."""
+    monkeypatch.setenv("FFT3D_Q16_MFMA", engine)
+    rng = np.random.default_rng(4400 + n)
+    x = workloads.sphere_grid(n, 4400 + n)[None]
+    xs = (x * (2.0 ** rng.integers(-60, 61, size=x.shape[:-1]))[..., None]).astype(np.complex64)
+    variants = [
+        (np.stack([bf16_bits(xs.real), bf16_bits(xs.imag)], axis=-1), np.zeros(x.shape[:-1], np.int8)),
+        (np.stack([bf16_bits(x.real), bf16_bits(x.imag)], axis=-1),
+         rng.integers(-110, 21, size=x.shape[:-1]).astype(np.int8)),
+    ]
+    for direction in (1, -1):
+        for pay, ex in variants:
+            plan = F.Plan(n, n, n, 1, "bf16", direction)
+            out = plan.exec(join(pay, ex))
+            torch.cuda.synchronize()
+            pout, eout = split(out, x.shape)
+            xin = oracle.q16_decode(pay, ex, oracle.FMT_BF16)
+            got = oracle.q16_decode(pout, eout, oracle.FMT_BF16)
+            assert rel(got, oracle.fft3d(xin, direction)) <= TOL16, (engine, n, direction)
+            check_storage_rule(pout, eout, "bf16")
