@@ -1,6 +1,6 @@
 """GPU parity of the FP32 path against the FP64 oracle, through the C ABI.
 
-Bar (spec tolerance for the FP32 form): relative L2 error <= 5e-6 per
+Bar for the FP32 form: relative L2 error <= 5e-6 per
 transform against the oracle on the very same complex64 inputs.
 """
 import numpy as np
