@@ -16,6 +16,17 @@
 //
 // Half-spectrum planes are [y][M+1] complex; the z pass is the ordinary
 // strided kernel over the half layout.
+//
+// Columns x = 0 and x = M of a plane are real along y in the forward pass
+// (X_0 and X_M of every row are real), and in the inverse only the real
+// parts of their y transforms are used.  Both passes therefore transform
+// M lines along y, not M + 1: column 0 carries c = a + i b, a and b the two
+// real columns.  The forward splits C = FFT(c) afterwards into the two
+// Hermitian transforms A_k = (C_k + conj C_{N-k}) / 2 and
+// B_k = (C_k - conj C_{N-k}) / (2i); the inverse packs beforehand
+// p = H(h_0) + i H(h_M) with H(h)_k = (h_k + conj h_{N-k}) / 2, whose inverse
+// transform is Re IFFT(h_0) + i Re IFFT(h_M).  M lines per plane keep the y
+// stages whole (65 lines of a 128 plane left one wave a second butterfly).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -34,20 +45,21 @@ struct RealGeom {
     static constexpr int M = N / 2, H = M + 1;
     static constexpr int RS = odd_stride(H);   // LDS row stride (complex values)
     static constexpr int WORDS = N * RS;
-    static constexpr int TX = threads_for<M>(N), TY = threads_for<N>(H);
-    static constexpr int T = TX > TY ? TX : TY;
+    static constexpr int TX = threads_for<M>(N), TY = threads_for<N>(M);
+    // at most 512 threads: two workgroups per compute unit at N = 128
+    static constexpr int T = (TX > TY ? TX : TY) > 512 ? 512 : (TX > TY ? TX : TY);
     static constexpr int PAIRS = M / 2 + 1;    // (k, M-k) pairs per row
 };
 
-// Forward split of one row in LDS (k in [0, M/2]); w = W_N^k.
+// Forward split of one row in LDS (k in [0, M/2]); w = W_N^k.  The two real
+// values X_0 and X_M go to slot 0 as X_0 + i X_M.
 template <int N>
 __device__ __forceinline__ void r2c_split(float2* row, int k, float2 w)
 {
     constexpr int M = N / 2;
     if (k == 0) {
         const float2 a = row[0];
-        row[0] = make_float2(a.x + a.y, 0.f);
-        row[M] = make_float2(a.x - a.y, 0.f);
+        row[0] = make_float2(a.x + a.y, a.x - a.y);
         return;
     }
     const float2 A = row[k], B = row[M - k];
@@ -58,13 +70,14 @@ __device__ __forceinline__ void r2c_split(float2* row, int k, float2 w)
     if (2 * k != M) row[M - k] = make_float2(E.x - WO.x, WO.y - E.y);
 }
 
-// Inverse merge of one row in LDS (k in [0, M/2]); w = W_N^{-k}.
+// Inverse merge of one row in LDS (k in [0, M/2]); w = W_N^{-k}.  Slot 0
+// holds Re h_0 + i Re h_M of the row (after the packed y transform).
 template <int N>
 __device__ __forceinline__ void c2r_merge(float2* row, int k, float2 w)
 {
     constexpr int M = N / 2;
     if (k == 0) {
-        const float a = row[0].x, b = row[M].x;
+        const float a = row[0].x, b = row[0].y;
         row[0] = make_float2(a + b, a - b);
         return;
     }
@@ -77,13 +90,58 @@ __device__ __forceinline__ void c2r_merge(float2* row, int k, float2 w)
     if (2 * k != M) row[M - k] = make_float2(P.x - Q.x, Q.y - P.y);
 }
 
-// y-pass store of a half-spectrum plane: line = x in [0, M], element = y.
-template <int N>
+// y-pass store of a half-spectrum plane: line = x in [0, M), element = y;
+// line 0 (the packed columns 0 and M) stays in the LDS tile (row stride RS)
+// for the split that follows.
+template <int N, int RS>
 struct HalfColOut {
     float2* p;
+    float2* lds;
     __device__ __forceinline__ float2 load(int, int) const { return float2{}; }
-    __device__ __forceinline__ void store(int x, int y, float2 v) const { p[y * (N / 2 + 1) + x] = v; }
+    __device__ __forceinline__ void store(int x, int y, float2 v) const
+    {
+        if (x == 0) lds[y * RS] = v;
+        else p[y * (N / 2 + 1) + x] = v;
+    }
 };
+
+// Forward: split the packed column C (slot 0 of every row of the tile) into
+// columns 0 and M of the half-spectrum plane.  A thread takes the pair
+// (k, N - k), so it reads only what it writes.
+template <int N, int RS, int T>
+__device__ __forceinline__ void r2c_unpack_cols(const float2* lds, float2* out, int tid)
+{
+    constexpr int M = N / 2, H = M + 1;
+    for (int k = tid; k <= N / 2; k += T) {
+        const int kn = (N - k) % N;
+        const float2 c = lds[k * RS], d = lds[kn * RS];
+        const float2 a = make_float2(0.5f * (c.x + d.x), 0.5f * (c.y - d.y));   // (C_k + conj C_{N-k}) / 2
+        const float2 q = make_float2(0.5f * (c.x - d.x), 0.5f * (c.y + d.y));   // (C_k - conj C_{N-k}) / 2
+        const float2 b = make_float2(q.y, -q.x);                                // q / i
+        out[k * H] = a;
+        out[k * H + M] = b;
+        if (kn != k) {   // A and B are Hermitian
+            out[kn * H] = make_float2(a.x, -a.y);
+            out[kn * H + M] = make_float2(b.x, -b.y);
+        }
+    }
+}
+
+// Inverse: pack columns 0 and M of the tile into slot 0 as
+// H(h_0) + i H(h_M).  A thread takes the pair (k, N - k).
+template <int N, int RS, int T>
+__device__ __forceinline__ void c2r_pack_cols(float2* lds, int tid)
+{
+    constexpr int M = N / 2;
+    for (int k = tid; k <= N / 2; k += T) {
+        const int kn = (N - k) % N;
+        const float2 h0k = lds[k * RS], h0n = lds[kn * RS], hmk = lds[k * RS + M], hmn = lds[kn * RS + M];
+        const float2 e = make_float2(0.5f * (h0k.x + h0n.x), 0.5f * (h0k.y - h0n.y));   // H(h_0)_k
+        const float2 f = make_float2(0.5f * (hmk.x + hmn.x), 0.5f * (hmk.y - hmn.y));   // H(h_M)_k
+        lds[k * RS] = make_float2(e.x - f.y, e.y + f.x);                              // e + i f
+        if (kn != k) lds[kn * RS] = make_float2(e.x + f.y, f.x - e.y);                // conj e + i conj f
+    }
+}
 
 // r2c plane pass (S = -1): real planes [planes][N][N] -> half-spectrum planes
 // [planes][N][M+1], x split then y transform.  Persistent over planes with
@@ -114,8 +172,10 @@ k_plane_r2c(const float* in, float2* out, const float2* __restrict__ tw_x, const
         }
         __syncthreads();
         const LdsAcc<1, RS> col{lds};
-        const HalfColOut<N> dst{out + p * N * H};
-        run_tail<N, S, H, T, 0, false>(col, dst, tw_y, tid);
+        const HalfColOut<N, RS> dst{out + p * N * H, lds};
+        run_tail<N, S, M, T, 0, false>(col, dst, tw_y, tid);
+        __syncthreads();
+        r2c_unpack_cols<N, RS, T>(lds, out + p * N * H, tid);
         __syncthreads();
     }
 }
@@ -141,7 +201,9 @@ k_plane_c2r(const float2* in, float* out, const float2* __restrict__ tw_x, const
         __syncthreads();
         const long pn = p + gridDim.x;
         if (pn < planes) regs.load(in + pn * N * H, tid);
-        fft_lds_all<N, S, H, T, 1, RS>(lds, tw_y, tid);
+        c2r_pack_cols<N, RS, T>(lds, tid);
+        __syncthreads();
+        fft_lds_all<N, S, M, T, 1, RS>(lds, tw_y, tid);
         for (int i = tid; i < N * G::PAIRS; i += T) {
             const int y = i / G::PAIRS, k = i % G::PAIRS;
             c2r_merge<N>(lds + y * RS, k, rt[k]);
