@@ -155,9 +155,11 @@ k_plane_r2c(const float* in, float2* out, const float2* __restrict__ tw_x, const
     using G = RealGeom<N>;
     constexpr int M = G::M, H = G::H, T = G::T, RS = G::RS;
     __shared__ float2 lds[G::WORDS];
+    __shared__ float2 rts[G::PAIRS];   // the split's twiddles, read by every plane
     const int tid = threadIdx.x;
     const float2* in2 = reinterpret_cast<const float2*>(in);
     TileRegs<N, M, T, stream_plane(N)> regs;
+    for (int k = tid; k < G::PAIRS; k += T) rts[k] = rt[k];   // visible after the first barrier below
     long p = blockIdx.x;
     if (p < planes) regs.load(in2 + p * N * M, tid);
     for (; p < planes; p += gridDim.x) {
@@ -168,7 +170,7 @@ k_plane_r2c(const float* in, float2* out, const float2* __restrict__ tw_x, const
         fft_lds_all<M, S, N, T, RS, 1>(lds, tw_x, tid);
         for (int i = tid; i < N * G::PAIRS; i += T) {
             const int y = i / G::PAIRS, k = i % G::PAIRS;
-            r2c_split<N>(lds + y * RS, k, rt[k]);
+            r2c_split<N>(lds + y * RS, k, rts[k]);
         }
         __syncthreads();
         const LdsAcc<1, RS> col{lds};
@@ -191,9 +193,11 @@ k_plane_c2r(const float2* in, float* out, const float2* __restrict__ tw_x, const
     using G = RealGeom<N>;
     constexpr int M = G::M, H = G::H, T = G::T, RS = G::RS;
     __shared__ float2 lds[G::WORDS];
+    __shared__ float2 rts[G::PAIRS];   // the merge's twiddles, read by every plane
     const int tid = threadIdx.x;
     float2* out2 = reinterpret_cast<float2*>(out);
     TileRegs<N, H, T, stream_plane(N)> regs;
+    for (int k = tid; k < G::PAIRS; k += T) rts[k] = rt[k];   // visible after the first barrier below
     long p = blockIdx.x;
     if (p < planes) regs.load(in + p * N * H, tid);
     for (; p < planes; p += gridDim.x) {
@@ -206,7 +210,7 @@ k_plane_c2r(const float2* in, float* out, const float2* __restrict__ tw_x, const
         fft_lds_all<N, S, M, T, 1, RS>(lds, tw_y, tid);
         for (int i = tid; i < N * G::PAIRS; i += T) {
             const int y = i / G::PAIRS, k = i % G::PAIRS;
-            c2r_merge<N>(lds + y * RS, k, rt[k]);
+            c2r_merge<N>(lds + y * RS, k, rts[k]);
         }
         __syncthreads();
         fft_lds_all<M, S, N, T, RS, 1>(lds, tw_x, tid);
