@@ -449,6 +449,16 @@ k_plane_pf(const float2* in, float2* out, const float2* __restrict__ tw, long pl
     constexpr int T = PlaneGeom<N>::T, RS = PlaneGeom<N>::RS;
     __shared__ float2 lds[PlaneGeom<N>::WORDS];
     const int tid = threadIdx.x;
+    // N not a multiple of 64: a wave's butterflies of one stage span two
+    // twiddle groups, so the stages read their twiddles per lane; those reads
+    // go to an LDS copy of the table instead of global memory
+    constexpr bool TWL = N % 64 != 0;
+    constexpr int TWN = Plan1D<N, K>::tw_len;
+    __shared__ float2 tw_lds[TWL && TWN > 0 ? TWN : 1];
+    if constexpr (TWL && TWN > 0) {
+        for (int i = tid; i < TWN; i += T) tw_lds[i] = tw[i];   // visible after the first barrier below
+        tw = tw_lds;
+    }
     TileRegs<N, N, T, NT> regs;
     FactorRegs<N, N, T> vr;
     float scale = 0.f;
