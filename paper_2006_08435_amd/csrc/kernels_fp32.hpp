@@ -1080,6 +1080,17 @@ k_axis_str(const float2* in, float2* out, const float2* __restrict__ tw, AxisMap
     static_assert(T % L == 0, "each thread keeps one line");
     __shared__ float2 lds[P::stages > 1 ? G::WORDS : 1];
     const int tid = threadIdx.x;
+    // tiles of fewer than 64 lines: a wave's butterflies span several twiddle
+    // groups and read their twiddles per lane, from an LDS copy of the table
+    // (stage 0 reads none; the barrier after it publishes the copy).  At
+    // 512^3 (32-line tiles) the y and z passes 0.392 / 0.465 -> 0.386 /
+    // 0.460 ms, at 4 x 256^3 0.169 / 0.211 -> 0.164 / 0.205 ms.
+    constexpr bool TWL = L % 64 != 0 && P::stages > 1 && P::tw_len > 0;
+    __shared__ float2 tw_lds[TWL ? P::tw_len : 1];
+    if constexpr (TWL) {
+        for (int i = tid; i < P::tw_len; i += T) tw_lds[i] = tw[i];
+        tw = tw_lds;
+    }
     const long tile = rev_tile();
     const long l0 = tile * L;
     const int myline = tid % L;
@@ -1385,6 +1396,9 @@ k_axis_row(const float2* in, float2* out, const float2* __restrict__ tw, long ro
     constexpr int T = G::T;
     __shared__ float2 lds[G::WORDS];
     const int tid = threadIdx.x;
+    // (an LDS copy of the twiddle table, as the strided pass makes for tiles
+    // of fewer than 64 lines, measured slower here: 0.385 -> 0.419 ms for the
+    // x pass of 512^3, one 4 KB table per 16-row tile)
     const long r0 = (long)blockIdx.x * L;
     const int valid = (int)((rows - r0) < L ? (rows - r0) : L);
     const long base = r0 * N;
