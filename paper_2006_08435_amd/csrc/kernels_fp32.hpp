@@ -1307,6 +1307,14 @@ k_axis_density(const float2* buf, const float2* __restrict__ tw, AxisMap m, int 
     constexpr int R0 = P::radix(0), M0 = N / R0, NB0 = L * M0, IT0 = (NB0 + T - 1) / T;
     __shared__ float2 lds[G::WORDS];
     const int tid = threadIdx.x;
+    // tiles of fewer than 64 lines read their twiddles per lane: from an LDS
+    // copy, made once for all orbitals (published by the first barrier)
+    constexpr bool TWL = L % 64 != 0 && P::stages > 1 && P::tw_len > 0;
+    __shared__ float2 tw_lds[TWL ? P::tw_len : 1];
+    if constexpr (TWL) {
+        for (int i = tid; i < P::tw_len; i += T) tw_lds[i] = tw[i];
+        tw = tw_lds;
+    }
     const long tile = rev_tile();
     const long l0 = tile * L;
     const int myline = tid % L;
