@@ -554,7 +554,7 @@ def bench_soak(args):
     L = _lib.lib()
     runs = []
     t_start = time.time()
-    for threads, chunk in ((1024, 2), (-1024, 2)):
+    for threads, chunk in ((1024, 1), (1024, 2), (-1024, 2)):   # the default schedule first
         plan = fft3d.PlanMany(groups, fft3d.FFT3D_INVERSE)
         plan.set_schedule(threads, chunk)
         plan.exec_ptrs(iptr, optr, sh)
