@@ -30,9 +30,10 @@
  * nx == ny == nz with 16 | n (16, 32, 48, 64, 80, 96, 128); all arithmetic
  * is FP32 (the radix-16 stage as an FP32 butterfly on the vector ALUs; with
  * the environment variable FFT3D_Q16_MFMA=1 at plan time it runs instead as
- * a DFT-matrix product with FP16 operands and FP32 accumulation on the
- * matrix cores); the intermediate between the xy and z passes is stored as
- * scaled binary16.
+ * a DFT-matrix product with FP32 accumulation on the matrix cores: binary16
+ * operands, or for bfloat16 input the payloads as loaded times a DFT matrix
+ * held as two bfloat16 terms); the intermediate between the xy and z passes
+ * is stored as scaled binary16.
  *
  * Memory: every data pointer passed to an exec call is a DEVICE pointer
  * (hipMalloc / torch CUDA tensor memory) on the device the plan was created
